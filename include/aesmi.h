@@ -1,0 +1,217 @@
+/*
+ * aesmi.h -- C ABI of the MI355X (gfx950) AES library.
+ *
+ * The library encrypts very many independent 16-byte blocks on one GPU: the
+ * AES cipher (key expansion; rounds of SubBytes, ShiftRows, MixColumns and
+ * AddRoundKey, the last round without MixColumns) in ECB and counter (CTR)
+ * mode, as framed algebraically in Kepner et al., arXiv 1506.08503 (sec. II,
+ * App. A1-A5).  128-, 192- and 256-bit keys (10, 12, 14 rounds).
+ *
+ * Conventions shared by every entry point
+ *  - Plain C types only.  Device buffers are raw device pointers; `stream` is
+ *    a hipStream_t passed as void* (NULL = the null stream).
+ *  - The caller owns every buffer.  No entry point allocates device memory.
+ *  - Launching entry points are stream-ordered and asynchronous: AES_OK means
+ *    the arguments passed validation and the work was enqueued on `stream`.
+ *    Argument errors are returned before any HIP call is made.
+ *  - Device data buffers must be 16-byte aligned.  in == out (in place) is
+ *    allowed; any other overlap of the input and output ranges is an error.
+ *  - nbytes == 0 is a no-op that returns AES_OK (pointers are not checked).
+ *  - Byte order: block k of a buffer is bytes [16k, 16k+16); byte j of a
+ *    block is state row j % 4, column j / 4 (the order the paper's ShiftRows
+ *    index vectors of App. A1 / A4 imply).
+ */
+#ifndef AESMI_H
+#define AESMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AES_OK = 0,
+    AES_ERR_NULL = -1,     /* a required pointer is NULL                        */
+    AES_ERR_KEYLEN = -2,   /* key length not 16, 24 or 32 bytes                 */
+    AES_ERR_LENGTH = -3,   /* ECB length not a multiple of 16                   */
+    AES_ERR_ALIGN = -4,    /* a device data pointer is not 16-byte aligned      */
+    AES_ERR_OVERLAP = -5,  /* input and output overlap without being equal      */
+    AES_ERR_COUNTER = -6,  /* CTR: ctr0 + number of blocks exceeds 2^32         */
+    AES_ERR_SEGMENT = -7,  /* batched: invalid segment table entry              */
+    AES_ERR_HIP = -8,      /* the HIP runtime reported an error                 */
+    AES_ERR_CONFIG = -9,   /* invalid launch configuration / workspace too small*/
+    AES_ERR_DEVICE = -10   /* no usable gfx950 device                           */
+} aes_status_t;
+
+/*
+ * Expanded key: the Nr + 1 round keys of the key schedule (App. A3 for 128-bit
+ * keys; FIPS-197 sec. 5.2 for 192 / 256).  Round key r, column c is
+ * rk_enc[4 r + c], a little-endian word whose byte j is state row j.
+ * rk_dec holds the keys of the equivalent inverse cipher: rk_dec[4 r + c] is
+ * column c of InvMixColumns(round key Nr - r) for 0 < r < Nr, and the plain
+ * round keys Nr and 0 at r = 0 and r = Nr.  Plain old data (488 bytes); it is
+ * valid in host or device memory and carries no pointers.
+ */
+typedef struct aes_key_schedule {
+    uint32_t nr;          /* 10, 12 or 14                                 */
+    uint32_t key_bytes;   /* 16, 24 or 32                                 */
+    uint32_t rk_enc[60];
+    uint32_t rk_dec[60];
+} aes_key_schedule_t;
+
+/* Kernel layout for the round function. */
+typedef enum {
+    AES_LAYOUT_AUTO = 0,      /* library default (the measured faster one)        */
+    AES_LAYOUT_TTABLE = 1,    /* lookup tables replicated in LDS per lane group     */
+    AES_LAYOUT_BITSLICE = 2   /* constant-time bitsliced: 32 blocks per lane word   */
+} aes_layout_t;
+
+/* Launch shape.  Zero fields take the library default. */
+typedef struct aes_launch {
+    uint32_t layout;          /* aes_layout_t                                    */
+    uint32_t wg_size;         /* threads per workgroup (multiple of 64, <= 1024) */
+    uint32_t grid_per_cu;     /* workgroups per compute unit                     */
+    uint32_t blocks_per_lane; /* 16-byte blocks a lane carries per iteration     */
+} aes_launch_t;
+
+/*
+ * aes_expand_key -- host key expansion (App. A3; FIPS-197 sec. 5.2).
+ *   key       host pointer, key_bytes bytes (16, 24 or 32)
+ *   ks_host   host output; fully overwritten
+ * Returns AES_ERR_NULL, AES_ERR_KEYLEN or AES_OK.  Pure host code, no GPU.
+ */
+aes_status_t aes_expand_key(const uint8_t *key, size_t key_bytes,
+                            aes_key_schedule_t *ks_host);
+
+/*
+ * aes_expand_keys_device -- key expansion of nkeys keys on the GPU, one key
+ * per lane (App. A3).  keys_dev: device, nkeys * key_bytes bytes, key i at
+ * offset i * key_bytes.  ks_dev: device array of nkeys schedules (output).
+ * Same validation as aes_expand_key; nkeys == 0 is a no-op.
+ */
+aes_status_t aes_expand_keys_device(const uint8_t *keys_dev, size_t key_bytes,
+                                    size_t nkeys, aes_key_schedule_t *ks_dev,
+                                    void *stream);
+
+/*
+ * aes_ecb_encrypt / aes_ecb_decrypt -- ECB (sec. II): each 16-byte block of
+ * in_dev is enciphered (App. A1 round sequence without the chaining) or
+ * deciphered (App. A4 without the chaining) on its own into out_dev.
+ *   ks_dev   device pointer to one key schedule
+ *   nbytes   multiple of 16, else AES_ERR_LENGTH
+ * The _ex forms take a launch shape (NULL = default).
+ */
+aes_status_t aes_ecb_encrypt(const aes_key_schedule_t *ks_dev, const void *in_dev,
+                             void *out_dev, size_t nbytes, void *stream);
+aes_status_t aes_ecb_decrypt(const aes_key_schedule_t *ks_dev, const void *in_dev,
+                             void *out_dev, size_t nbytes, void *stream);
+aes_status_t aes_ecb_encrypt_ex(const aes_key_schedule_t *ks_dev, const void *in_dev,
+                                void *out_dev, size_t nbytes,
+                                const aes_launch_t *launch, void *stream);
+aes_status_t aes_ecb_decrypt_ex(const aes_key_schedule_t *ks_dev, const void *in_dev,
+                                void *out_dev, size_t nbytes,
+                                const aes_launch_t *launch, void *stream);
+
+/*
+ * aes_ctr_xcrypt -- counter mode (not in the paper; the cipher of sec. II
+ * applied to counter blocks): keystream block i is the encryption of
+ * nonce[0..11] followed by the big-endian 32-bit value ctr0 + i, and
+ * out = in XOR keystream.  A short last block uses the first nbytes % 16
+ * keystream bytes.  The same call decrypts.
+ *   nonce    HOST pointer to 12 bytes (copied into the launch)
+ *   nbytes   any length; ctr0 + ceil(nbytes / 16) must be <= 2^32, else
+ *            AES_ERR_COUNTER (the counter never wraps silently)
+ */
+aes_status_t aes_ctr_xcrypt(const aes_key_schedule_t *ks_dev, const uint8_t *nonce,
+                            uint32_t ctr0, const void *in_dev, void *out_dev,
+                            size_t nbytes, void *stream);
+aes_status_t aes_ctr_xcrypt_ex(const aes_key_schedule_t *ks_dev, const uint8_t *nonce,
+                               uint32_t ctr0, const void *in_dev, void *out_dev,
+                               size_t nbytes, const aes_launch_t *launch,
+                               void *stream);
+
+/*
+ * Batched CTR: many messages, each with its own key schedule, nonce and
+ * counter, in one persistent launch (the per-row V and K of sec. II applied to
+ * messages of uneven length).  Message s reads nbytes bytes at
+ * in_base + in_off and writes them at out_base + out_off, exactly as
+ * aes_ctr_xcrypt would with ks_table[key_slot], its nonce and ctr0.
+ */
+typedef struct aes_segment {
+    uint64_t in_off;      /* byte offset of the message in in_base (16-aligned)  */
+    uint64_t out_off;     /* byte offset in out_base (16-aligned)                */
+    uint64_t nbytes;      /* message length, any value >= 0                      */
+    uint32_t key_slot;    /* index into ks_table                                  */
+    uint32_t ctr0;        /* first counter value                                  */
+    uint8_t  nonce[12];
+    uint32_t reserved;    /* must be 0                                            */
+} aes_segment_t;          /* 48 bytes */
+
+/* Tuning of the batched launch.  Zero fields take the library default. */
+typedef struct aes_batch_tune {
+    uint32_t layout;          /* aes_layout_t                                  */
+    uint32_t wg_size;         /* threads per workgroup                         */
+    uint32_t grid_per_cu;     /* persistent workgroups per compute unit        */
+    uint32_t tile_blocks;     /* 16-byte blocks per tile claimed by a wave     */
+} aes_batch_tune_t;
+
+/*
+ * Workspace the batched call needs (device bytes, 256-byte aligned by the
+ * caller) for nsegs segments: the per-segment tile prefix sums, the tile
+ * counter and the device status word.
+ */
+size_t aes_batched_workspace_bytes(uint32_t nsegs);
+
+/*
+ * aes_ctr_xcrypt_batched -- one persistent launch over a device segment table.
+ *   segs_dev    device array of nsegs segments
+ *   nkeys       number of schedules in ks_table_dev (key_slot must be < nkeys)
+ *   ws_dev      device workspace of at least aes_batched_workspace_bytes(nsegs)
+ *   tune        host pointer or NULL
+ * Segment errors (bad slot, misaligned offset, counter overflow, reserved != 0)
+ * are found on the device: that segment is skipped and the status word in the
+ * workspace becomes AES_ERR_SEGMENT; read it after the stream completes with
+ * aes_batched_read_status.  Messages must not overlap each other's output.
+ */
+aes_status_t aes_ctr_xcrypt_batched(const aes_segment_t *segs_dev, uint32_t nsegs,
+                                    const aes_key_schedule_t *ks_table_dev,
+                                    uint32_t nkeys, const uint8_t *in_base_dev,
+                                    uint8_t *out_base_dev, const aes_batch_tune_t *tune,
+                                    void *ws_dev, size_t ws_bytes, void *stream);
+
+/* Status word of the last batched call that used ws_dev (synchronous copy on
+ * `stream`; call after the batched launch). */
+aes_status_t aes_batched_read_status(const void *ws_dev, void *stream,
+                                     int32_t *status_out);
+
+/*
+ * Graph form of the batched call: captures aes_ctr_xcrypt_batched with fixed
+ * pointers into a HIP graph.  The caller may rewrite the contents of segs_dev,
+ * the input and the key table between launches (nsegs is fixed per graph).
+ */
+typedef struct aes_batched_graph aes_batched_graph_t;
+aes_status_t aes_batched_graph_create(const aes_segment_t *segs_dev, uint32_t nsegs,
+                                      const aes_key_schedule_t *ks_table_dev,
+                                      uint32_t nkeys, const uint8_t *in_base_dev,
+                                      uint8_t *out_base_dev,
+                                      const aes_batch_tune_t *tune, void *ws_dev,
+                                      size_t ws_bytes, void *stream,
+                                      aes_batched_graph_t **graph_out);
+aes_status_t aes_batched_graph_launch(aes_batched_graph_t *graph, void *stream);
+aes_status_t aes_batched_graph_destroy(aes_batched_graph_t *graph);
+
+/* Text for a status code (static storage). */
+const char *aes_status_string(aes_status_t status);
+
+/* Library version, and the number of compute units of the current device
+ * (0 when no device is usable). */
+const char *aes_version(void);
+int aes_device_cu_count(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AESMI_H */

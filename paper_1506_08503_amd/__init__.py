@@ -1,0 +1,20 @@
+"""MI355X (gfx950) AES for very many independent 16-byte blocks.
+
+Kepner et al., "Parallel Vectorized Algebraic AES in MATLAB ..." (arXiv
+1506.08503) frames AES as GF(2^8) algebra vectorized over many messages; this
+package runs that cipher (ECB and CTR, 128/192/256-bit keys) as hand-written
+HIP kernels behind the C ABI in ``include/aesmi.h``.  ``aesmi`` is the thin
+Python binding; ``batch`` and ``serve`` add many-message batching and a
+continuous-batching request loop on top.
+"""
+from .aesmi import (AesError, KeySchedule, Launch, Segment, BatchTune, lib, expand_key,
+                    schedule_to_device, key_schedule, expand_keys_device, ecb_encrypt,
+                    ecb_decrypt, ctr_xcrypt, device_cu_count, header_functions,
+                    LAYOUT_AUTO, LAYOUT_TTABLE, LAYOUT_BITSLICE, SCHEDULE_BYTES,
+                    SEGMENT_BYTES, STATUS)
+
+__all__ = ["AesError", "KeySchedule", "Launch", "Segment", "BatchTune", "lib", "expand_key",
+           "schedule_to_device", "key_schedule", "expand_keys_device", "ecb_encrypt",
+           "ecb_decrypt", "ctr_xcrypt", "device_cu_count", "header_functions",
+           "LAYOUT_AUTO", "LAYOUT_TTABLE", "LAYOUT_BITSLICE", "SCHEDULE_BYTES",
+           "SEGMENT_BYTES", "STATUS"]

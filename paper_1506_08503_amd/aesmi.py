@@ -1,0 +1,245 @@
+"""Python binding of libaesmi (ctypes).
+
+Argument marshalling only: every step of the cipher runs in the library's HIP
+kernels.  PyTorch supplies device memory (uint8 CUDA tensors) and the current
+HIP stream.  If ``libaesmi.so`` is missing the first call raises: there is no
+fallback path.
+
+The C entry points keep their names: ``aes_expand_key`` is ``expand_key``,
+``aes_ctr_xcrypt`` is ``ctr_xcrypt`` and so on.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaesmi.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "aesmi.h")
+
+AES_OK = 0
+STATUS = {0: "AES_OK", -1: "AES_ERR_NULL", -2: "AES_ERR_KEYLEN", -3: "AES_ERR_LENGTH",
+          -4: "AES_ERR_ALIGN", -5: "AES_ERR_OVERLAP", -6: "AES_ERR_COUNTER",
+          -7: "AES_ERR_SEGMENT", -8: "AES_ERR_HIP", -9: "AES_ERR_CONFIG",
+          -10: "AES_ERR_DEVICE"}
+LAYOUT_AUTO, LAYOUT_TTABLE, LAYOUT_BITSLICE = 0, 1, 2
+SCHEDULE_BYTES = 488
+SEGMENT_BYTES = 48
+
+
+class AesError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        name = STATUS.get(status, str(status))
+        text = _lib.aes_status_string(status).decode() if _lib is not None else name
+        super().__init__("%s%s: %s" % (what + ": " if what else "", name, text))
+
+
+class KeySchedule(ctypes.Structure):
+    _fields_ = [("nr", ctypes.c_uint32), ("key_bytes", ctypes.c_uint32),
+                ("rk_enc", ctypes.c_uint32 * 60), ("rk_dec", ctypes.c_uint32 * 60)]
+
+    def to_bytes(self) -> bytes:
+        return ctypes.string_at(ctypes.addressof(self), ctypes.sizeof(self))
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("layout", ctypes.c_uint32), ("wg_size", ctypes.c_uint32),
+                ("grid_per_cu", ctypes.c_uint32), ("blocks_per_lane", ctypes.c_uint32)]
+
+
+class Segment(ctypes.Structure):
+    _fields_ = [("in_off", ctypes.c_uint64), ("out_off", ctypes.c_uint64),
+                ("nbytes", ctypes.c_uint64), ("key_slot", ctypes.c_uint32),
+                ("ctr0", ctypes.c_uint32), ("nonce", ctypes.c_uint8 * 12),
+                ("reserved", ctypes.c_uint32)]
+
+
+class BatchTune(ctypes.Structure):
+    _fields_ = [("layout", ctypes.c_uint32), ("wg_size", ctypes.c_uint32),
+                ("grid_per_cu", ctypes.c_uint32), ("tile_blocks", ctypes.c_uint32)]
+
+
+assert ctypes.sizeof(KeySchedule) == SCHEDULE_BYTES
+assert ctypes.sizeof(Segment) == SEGMENT_BYTES
+
+_lib = None
+
+
+def header_functions(path: str = HEADER) -> list[str]:
+    """Names of every function the C header declares."""
+    with open(path) as f:
+        text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+    return sorted(set(re.findall(r"\b(aes_\w+)\s*\(", text)))
+
+
+def lib():
+    """The loaded libaesmi.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libaesmi.so is not built (python -m paper_1506_08503_amd.build); "
+                               "there is no fallback implementation")
+        l = ctypes.CDLL(LIB_PATH)
+        vp, sz, u32, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_int32
+        st = ctypes.c_int
+        sig = {
+            "aes_expand_key": ([vp, sz, ctypes.POINTER(KeySchedule)], st),
+            "aes_expand_keys_device": ([vp, sz, sz, vp, vp], st),
+            "aes_ecb_encrypt": ([vp, vp, vp, sz, vp], st),
+            "aes_ecb_decrypt": ([vp, vp, vp, sz, vp], st),
+            "aes_ecb_encrypt_ex": ([vp, vp, vp, sz, ctypes.POINTER(Launch), vp], st),
+            "aes_ecb_decrypt_ex": ([vp, vp, vp, sz, ctypes.POINTER(Launch), vp], st),
+            "aes_ctr_xcrypt": ([vp, vp, u32, vp, vp, sz, vp], st),
+            "aes_ctr_xcrypt_ex": ([vp, vp, u32, vp, vp, sz, ctypes.POINTER(Launch), vp], st),
+            "aes_batched_workspace_bytes": ([u32], sz),
+            "aes_ctr_xcrypt_batched": ([vp, u32, vp, u32, vp, vp, ctypes.POINTER(BatchTune),
+                                        vp, sz, vp], st),
+            "aes_batched_read_status": ([vp, vp, ctypes.POINTER(i32)], st),
+            "aes_batched_graph_create": ([vp, u32, vp, u32, vp, vp, ctypes.POINTER(BatchTune),
+                                          vp, sz, vp, ctypes.POINTER(vp)], st),
+            "aes_batched_graph_launch": ([vp, vp], st),
+            "aes_batched_graph_destroy": ([vp], st),
+            "aes_status_string": ([st], ctypes.c_char_p),
+            "aes_version": ([], ctypes.c_char_p),
+            "aes_device_cu_count": ([], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(l, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = l
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != AES_OK:
+        raise AesError(status, what)
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _dev_u8(t: torch.Tensor, name: str):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or not t.is_cuda:
+        raise TypeError("%s must be a uint8 CUDA tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------------- key schedule
+def expand_key(key: bytes) -> KeySchedule:
+    """aes_expand_key: host key expansion (16, 24 or 32-byte key)."""
+    key = bytes(key)
+    ks = KeySchedule()
+    buf = ctypes.create_string_buffer(key, len(key))
+    _check(lib().aes_expand_key(buf, len(key), ctypes.byref(ks)), "aes_expand_key")
+    return ks
+
+
+def schedule_to_device(ks: KeySchedule, device="cuda") -> torch.Tensor:
+    """Copy a host schedule into a 488-byte device tensor."""
+    host = torch.frombuffer(bytearray(ks.to_bytes()), dtype=torch.uint8)
+    return host.to(device)
+
+
+def key_schedule(key: bytes, device="cuda") -> torch.Tensor:
+    return schedule_to_device(expand_key(key), device)
+
+
+def expand_keys_device(keys: torch.Tensor) -> torch.Tensor:
+    """aes_expand_keys_device: keys is an (n, key_bytes) uint8 CUDA tensor;
+    returns an (n, 488) uint8 CUDA tensor of schedules."""
+    _dev_u8(keys, "keys")
+    if keys.dim() != 2:
+        raise ValueError("keys must be (n, key_bytes)")
+    n, kb = keys.shape
+    out = torch.empty((n, SCHEDULE_BYTES), dtype=torch.uint8, device=keys.device)
+    with torch.cuda.device(keys.device):
+        _check(lib().aes_expand_keys_device(_ptr(keys), kb, n, _ptr(out), _stream(keys)),
+               "aes_expand_keys_device")
+    return out
+
+
+def _launch(layout=None, wg_size=0, grid_per_cu=0, blocks_per_lane=0):
+    if layout is None and not (wg_size or grid_per_cu or blocks_per_lane):
+        return None
+    return Launch(layout or 0, wg_size, grid_per_cu, blocks_per_lane)
+
+
+def _ks_arg(ks: torch.Tensor):
+    _dev_u8(ks, "key schedule")
+    if ks.numel() != SCHEDULE_BYTES:
+        raise ValueError("key schedule tensor must hold exactly one 488-byte schedule")
+    return _ptr(ks)
+
+
+def _out_like(x, out):
+    if out is None:
+        out = torch.empty_like(x)
+    _dev_u8(out, "out")
+    if out.numel() != x.numel():
+        raise ValueError("out must have as many bytes as the input")
+    return out
+
+
+# ---------------------------------------------------------------------- ECB
+def _ecb(fname, ks, x, out, launch):
+    _dev_u8(x, "input")
+    out = _out_like(x, out)
+    l = lib()
+    with torch.cuda.device(x.device):
+        if launch is None:
+            st = getattr(l, fname)(_ks_arg(ks), _ptr(x), _ptr(out), x.numel(), _stream(x))
+        else:
+            st = getattr(l, fname + "_ex")(_ks_arg(ks), _ptr(x), _ptr(out), x.numel(),
+                                           ctypes.byref(launch), _stream(x))
+    _check(st, fname)
+    return out
+
+
+def ecb_encrypt(ks: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None = None,
+                **launch) -> torch.Tensor:
+    """aes_ecb_encrypt: every 16-byte block of x enciphered independently."""
+    return _ecb("aes_ecb_encrypt", ks, x, out, _launch(**launch))
+
+
+def ecb_decrypt(ks: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None = None,
+                **launch) -> torch.Tensor:
+    """aes_ecb_decrypt: every 16-byte block of x deciphered independently."""
+    return _ecb("aes_ecb_decrypt", ks, x, out, _launch(**launch))
+
+
+# ---------------------------------------------------------------------- CTR
+def ctr_xcrypt(ks: torch.Tensor, nonce: bytes, ctr0: int, x: torch.Tensor,
+               out: torch.Tensor | None = None, **launch) -> torch.Tensor:
+    """aes_ctr_xcrypt: out = x XOR E(nonce || BE32(ctr0 + i)) block by block."""
+    _dev_u8(x, "input")
+    nonce = bytes(nonce)
+    if len(nonce) != 12:
+        raise ValueError("nonce must be 12 bytes")
+    out = _out_like(x, out)
+    nb = ctypes.create_string_buffer(nonce, 12)
+    lc = _launch(**launch)
+    l = lib()
+    with torch.cuda.device(x.device):
+        if lc is None:
+            st = l.aes_ctr_xcrypt(_ks_arg(ks), nb, ctr0, _ptr(x), _ptr(out), x.numel(),
+                                  _stream(x))
+        else:
+            st = l.aes_ctr_xcrypt_ex(_ks_arg(ks), nb, ctr0, _ptr(x), _ptr(out), x.numel(),
+                                     ctypes.byref(lc), _stream(x))
+    _check(st, "aes_ctr_xcrypt")
+    return out
+
+
+def device_cu_count() -> int:
+    return int(lib().aes_device_cu_count())

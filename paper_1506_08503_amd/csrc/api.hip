@@ -1,0 +1,351 @@
+// api.hip -- the C ABI of libaesmi: argument validation, dispatch to the
+// kernels, host key expansion and the batched-graph object.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <new>
+#include <string.h>
+
+#include "aes_tables.hpp"
+#include "aesmi.h"
+#include "internal.hpp"
+#include "keysched.hpp"
+
+namespace aesmi {
+
+int device_cu_count()
+{
+    static std::mutex mu;
+    static int cached[64];
+    static bool init = false;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!init) {
+        for (int &c : cached)
+            c = -1;
+        init = true;
+    }
+    if (cached[dev] < 0) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cu = 0;
+        cached[dev] = cu;
+    }
+    return cached[dev];
+}
+
+aes_status_t expand_key_host(const uint8_t *key, size_t key_bytes, aes_key_schedule_t *ks)
+{
+    if (!key || !ks)
+        return AES_ERR_NULL;
+    if (key_bytes != 16 && key_bytes != 24 && key_bytes != 32)
+        return AES_ERR_KEYLEN;
+    expand_schedule(key, (uint32_t)key_bytes, ks, kTables.sbox);
+    return AES_OK;
+}
+
+}  // namespace aesmi
+
+using namespace aesmi;
+
+namespace {
+
+bool aligned16(const void *p)
+{
+    return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+}
+
+// in == out is fine; any other intersection of [in, in+n) and [out, out+n) is not.
+bool bad_overlap(const void *in, const void *out, size_t n)
+{
+    uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
+    if (a == b)
+        return false;
+    return a < b + n && b < a + n;
+}
+
+aes_status_t from_hip(hipError_t e)
+{
+    return e == hipSuccess ? AES_OK : AES_ERR_HIP;
+}
+
+uint32_t layout_of(const aes_launch_t *launch)
+{
+    return launch ? launch->layout : (uint32_t)AES_LAYOUT_AUTO;
+}
+
+bool valid_launch(const aes_launch_t *launch)
+{
+    if (!launch)
+        return true;
+    if (launch->layout > AES_LAYOUT_BITSLICE)
+        return false;
+    if (launch->wg_size && (launch->wg_size % 64 || launch->wg_size > 1024))
+        return false;
+    if (launch->blocks_per_lane && launch->blocks_per_lane != 1 &&
+        launch->blocks_per_lane != 2 && launch->blocks_per_lane != 4)
+        return false;
+    if (launch->grid_per_cu > 64)
+        return false;
+    return true;
+}
+
+aes_status_t ecb_common(bool decrypt, const aes_key_schedule_t *ks, const void *in, void *out,
+                        size_t nbytes, const aes_launch_t *launch, void *stream)
+{
+    if (nbytes == 0)
+        return AES_OK;
+    if (!ks || !in || !out)
+        return AES_ERR_NULL;
+    if (nbytes % 16)
+        return AES_ERR_LENGTH;
+    if (!aligned16(in) || !aligned16(out))
+        return AES_ERR_ALIGN;
+    if (bad_overlap(in, out, nbytes))
+        return AES_ERR_OVERLAP;
+    if (!valid_launch(launch))
+        return AES_ERR_CONFIG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (layout_of(launch) == AES_LAYOUT_BITSLICE)
+        return from_hip(bitslice_ecb(decrypt, ks, in, out, nbytes / 16, launch, s));
+    return from_hip(ttable_ecb(decrypt, ks, in, out, nbytes / 16, launch, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+aes_status_t aes_expand_key(const uint8_t *key, size_t key_bytes, aes_key_schedule_t *ks_host)
+{
+    return expand_key_host(key, key_bytes, ks_host);
+}
+
+aes_status_t aes_expand_keys_device(const uint8_t *keys_dev, size_t key_bytes, size_t nkeys,
+                                    aes_key_schedule_t *ks_dev, void *stream)
+{
+    if (key_bytes != 16 && key_bytes != 24 && key_bytes != 32)
+        return AES_ERR_KEYLEN;
+    if (nkeys == 0)
+        return AES_OK;
+    if (!keys_dev || !ks_dev)
+        return AES_ERR_NULL;
+    return from_hip(expand_keys_device(keys_dev, (uint32_t)key_bytes, nkeys, ks_dev,
+                                       static_cast<hipStream_t>(stream)));
+}
+
+aes_status_t aes_ecb_encrypt(const aes_key_schedule_t *ks_dev, const void *in_dev,
+                             void *out_dev, size_t nbytes, void *stream)
+{
+    return ecb_common(false, ks_dev, in_dev, out_dev, nbytes, nullptr, stream);
+}
+
+aes_status_t aes_ecb_decrypt(const aes_key_schedule_t *ks_dev, const void *in_dev,
+                             void *out_dev, size_t nbytes, void *stream)
+{
+    return ecb_common(true, ks_dev, in_dev, out_dev, nbytes, nullptr, stream);
+}
+
+aes_status_t aes_ecb_encrypt_ex(const aes_key_schedule_t *ks_dev, const void *in_dev,
+                                void *out_dev, size_t nbytes, const aes_launch_t *launch,
+                                void *stream)
+{
+    return ecb_common(false, ks_dev, in_dev, out_dev, nbytes, launch, stream);
+}
+
+aes_status_t aes_ecb_decrypt_ex(const aes_key_schedule_t *ks_dev, const void *in_dev,
+                                void *out_dev, size_t nbytes, const aes_launch_t *launch,
+                                void *stream)
+{
+    return ecb_common(true, ks_dev, in_dev, out_dev, nbytes, launch, stream);
+}
+
+aes_status_t aes_ctr_xcrypt_ex(const aes_key_schedule_t *ks_dev, const uint8_t *nonce,
+                               uint32_t ctr0, const void *in_dev, void *out_dev, size_t nbytes,
+                               const aes_launch_t *launch, void *stream)
+{
+    if (nbytes == 0)
+        return AES_OK;
+    if (!ks_dev || !nonce || !in_dev || !out_dev)
+        return AES_ERR_NULL;
+    if (!aligned16(in_dev) || !aligned16(out_dev))
+        return AES_ERR_ALIGN;
+    if (bad_overlap(in_dev, out_dev, nbytes))
+        return AES_ERR_OVERLAP;
+    const uint64_t nblocks = ((uint64_t)nbytes + 15u) / 16u;
+    if ((uint64_t)ctr0 + nblocks > (1ull << 32))
+        return AES_ERR_COUNTER;
+    if (!valid_launch(launch))
+        return AES_ERR_CONFIG;
+    uint32_t nw[3];
+    for (int c = 0; c < 3; ++c)
+        nw[c] = (uint32_t)nonce[4 * c] | ((uint32_t)nonce[4 * c + 1] << 8) |
+                ((uint32_t)nonce[4 * c + 2] << 16) | ((uint32_t)nonce[4 * c + 3] << 24);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (layout_of(launch) == AES_LAYOUT_BITSLICE)
+        return from_hip(bitslice_ctr(ks_dev, nw, ctr0, in_dev, out_dev, nbytes, launch, s));
+    return from_hip(ttable_ctr(ks_dev, nw, ctr0, in_dev, out_dev, nbytes, launch, s));
+}
+
+aes_status_t aes_ctr_xcrypt(const aes_key_schedule_t *ks_dev, const uint8_t *nonce,
+                            uint32_t ctr0, const void *in_dev, void *out_dev, size_t nbytes,
+                            void *stream)
+{
+    return aes_ctr_xcrypt_ex(ks_dev, nonce, ctr0, in_dev, out_dev, nbytes, nullptr, stream);
+}
+
+size_t aes_batched_workspace_bytes(uint32_t nsegs)
+{
+    return batched_workspace_bytes(nsegs);
+}
+
+aes_status_t aes_ctr_xcrypt_batched(const aes_segment_t *segs_dev, uint32_t nsegs,
+                                    const aes_key_schedule_t *ks_table_dev, uint32_t nkeys,
+                                    const uint8_t *in_base_dev, uint8_t *out_base_dev,
+                                    const aes_batch_tune_t *tune, void *ws_dev, size_t ws_bytes,
+                                    void *stream)
+{
+    if (nsegs == 0)
+        return AES_OK;
+    if (!segs_dev || !ks_table_dev || !in_base_dev || !out_base_dev || !ws_dev)
+        return AES_ERR_NULL;
+    if (nkeys == 0)
+        return AES_ERR_SEGMENT;
+    if (!aligned16(in_base_dev) || !aligned16(out_base_dev) || !aligned16(segs_dev) ||
+        (reinterpret_cast<uintptr_t>(ws_dev) & 255u))
+        return AES_ERR_ALIGN;
+    if (ws_bytes < batched_workspace_bytes(nsegs))
+        return AES_ERR_CONFIG;
+    if (tune) {
+        if (tune->layout > AES_LAYOUT_BITSLICE)
+            return AES_ERR_CONFIG;
+        if (tune->wg_size && (tune->wg_size % 64 || tune->wg_size > 1024))
+            return AES_ERR_CONFIG;
+        if (tune->grid_per_cu > 64)
+            return AES_ERR_CONFIG;
+        if (tune->tile_blocks && (tune->tile_blocks % 64 || tune->tile_blocks > (1u << 20)))
+            return AES_ERR_CONFIG;
+    }
+    return from_hip(batched_ctr(segs_dev, nsegs, ks_table_dev, nkeys, in_base_dev,
+                                out_base_dev, tune, ws_dev, static_cast<hipStream_t>(stream)));
+}
+
+aes_status_t aes_batched_read_status(const void *ws_dev, void *stream, int32_t *status_out)
+{
+    if (!ws_dev || !status_out)
+        return AES_ERR_NULL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t v = 0;
+    hipError_t e = hipMemcpyAsync(&v, ws_dev, sizeof(v), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return AES_ERR_HIP;
+    *status_out = v;
+    return AES_OK;
+}
+
+struct aes_batched_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+aes_status_t aes_batched_graph_create(const aes_segment_t *segs_dev, uint32_t nsegs,
+                                      const aes_key_schedule_t *ks_table_dev, uint32_t nkeys,
+                                      const uint8_t *in_base_dev, uint8_t *out_base_dev,
+                                      const aes_batch_tune_t *tune, void *ws_dev,
+                                      size_t ws_bytes, void *stream,
+                                      aes_batched_graph_t **graph_out)
+{
+    if (!graph_out)
+        return AES_ERR_NULL;
+    *graph_out = nullptr;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipStream_t cap = s;
+    bool own = false;
+    if (!s) {
+        // The null stream cannot be captured: record on a private stream.
+        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+            return AES_ERR_HIP;
+        own = true;
+    }
+    hipGraph_t g = nullptr;
+    aes_status_t st = AES_OK;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        st = AES_ERR_HIP;
+    } else {
+        st = aes_ctr_xcrypt_batched(segs_dev, nsegs, ks_table_dev, nkeys, in_base_dev,
+                                    out_base_dev, tune, ws_dev, ws_bytes, cap);
+        hipError_t e = hipStreamEndCapture(cap, &g);
+        if (st == AES_OK && e != hipSuccess)
+            st = AES_ERR_HIP;
+    }
+    if (own)
+        (void)hipStreamDestroy(cap);
+    if (st != AES_OK) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return st;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return AES_ERR_HIP;
+    }
+    aes_batched_graph_t *obj = new (std::nothrow) aes_batched_graph_t{g, ex};
+    if (!obj) {
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGraphDestroy(g);
+        return AES_ERR_HIP;
+    }
+    *graph_out = obj;
+    return AES_OK;
+}
+
+aes_status_t aes_batched_graph_launch(aes_batched_graph_t *graph, void *stream)
+{
+    if (!graph)
+        return AES_ERR_NULL;
+    return from_hip(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)));
+}
+
+aes_status_t aes_batched_graph_destroy(aes_batched_graph_t *graph)
+{
+    if (!graph)
+        return AES_OK;
+    hipError_t e1 = hipGraphExecDestroy(graph->exec);
+    hipError_t e2 = hipGraphDestroy(graph->graph);
+    delete graph;
+    return (e1 == hipSuccess && e2 == hipSuccess) ? AES_OK : AES_ERR_HIP;
+}
+
+const char *aes_status_string(aes_status_t status)
+{
+    switch (status) {
+    case AES_OK: return "ok";
+    case AES_ERR_NULL: return "null pointer";
+    case AES_ERR_KEYLEN: return "key length must be 16, 24 or 32 bytes";
+    case AES_ERR_LENGTH: return "ECB length must be a multiple of 16 bytes";
+    case AES_ERR_ALIGN: return "device pointer not 16-byte aligned";
+    case AES_ERR_OVERLAP: return "input and output overlap without being equal";
+    case AES_ERR_COUNTER: return "counter range exceeds 2^32 blocks";
+    case AES_ERR_SEGMENT: return "invalid segment table entry";
+    case AES_ERR_HIP: return "HIP runtime error";
+    case AES_ERR_CONFIG: return "invalid launch configuration or workspace";
+    case AES_ERR_DEVICE: return "no usable gfx950 device";
+    }
+    return "unknown status";
+}
+
+const char *aes_version(void)
+{
+    return "aesmi 0.1 (gfx950)";
+}
+
+int aes_device_cu_count(void)
+{
+    return device_cu_count();
+}
+
+}  // extern "C"

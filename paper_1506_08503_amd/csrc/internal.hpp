@@ -1,0 +1,52 @@
+// internal.hpp -- launchers shared between the translation units of libaesmi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "aesmi.h"
+
+namespace aesmi {
+
+// Resolved launch shape of one kernel launch.
+struct Shape {
+    uint32_t wg;      // threads per workgroup
+    uint32_t grid;    // workgroups
+    uint32_t bpl;     // blocks per lane per loop iteration (1, 2 or 4)
+};
+
+// Compute units of the current device (cached per device; 0 if none).
+int device_cu_count();
+
+// --- T-table kernels (ttable.hip) ------------------------------------------
+// Full 16-byte blocks only for ECB; CTR handles a ragged tail itself.
+hipError_t ttable_ecb(bool decrypt, const aes_key_schedule_t *ks, const void *in,
+                      void *out, uint64_t nblocks, const aes_launch_t *launch,
+                      hipStream_t stream);
+hipError_t ttable_ctr(const aes_key_schedule_t *ks, const uint32_t nonce_words[3],
+                      uint32_t ctr0, const void *in, void *out, uint64_t nbytes,
+                      const aes_launch_t *launch, hipStream_t stream);
+
+// --- bitsliced kernels (bitslice.hip) --------------------------------------
+hipError_t bitslice_ecb(bool decrypt, const aes_key_schedule_t *ks, const void *in,
+                        void *out, uint64_t nblocks, const aes_launch_t *launch,
+                        hipStream_t stream);
+hipError_t bitslice_ctr(const aes_key_schedule_t *ks, const uint32_t nonce_words[3],
+                        uint32_t ctr0, const void *in, void *out, uint64_t nbytes,
+                        const aes_launch_t *launch, hipStream_t stream);
+
+// --- device key expansion (keyexp.hip) -------------------------------------
+hipError_t expand_keys_device(const uint8_t *keys, uint32_t key_bytes, uint64_t nkeys,
+                              aes_key_schedule_t *ks, hipStream_t stream);
+
+// --- batched persistent kernel (batched.hip) -------------------------------
+size_t batched_workspace_bytes(uint32_t nsegs);
+hipError_t batched_ctr(const aes_segment_t *segs, uint32_t nsegs,
+                       const aes_key_schedule_t *ks_table, uint32_t nkeys,
+                       const uint8_t *in_base, uint8_t *out_base,
+                       const aes_batch_tune_t *tune, void *ws, hipStream_t stream);
+
+// Host key expansion into the public struct (api.hip).
+aes_status_t expand_key_host(const uint8_t *key, size_t key_bytes, aes_key_schedule_t *ks);
+
+}  // namespace aesmi

@@ -1,0 +1,58 @@
+// keyexp.hip -- key expansion of many keys at once, one key per lane.
+//
+// Used when thousands of messages each bring their own key (the per-row key
+// tensor K of sec. II): the schedules are built on the device, next to the
+// data, instead of being expanded on the host and copied over.
+#include <hip/hip_runtime.h>
+
+#include "aes_tables.hpp"
+#include "internal.hpp"
+#include "keysched.hpp"
+
+namespace aesmi {
+namespace {
+
+__constant__ uint8_t g_sbox[256] = {
+#define X(i) kTables.sbox[i]
+#define X8(i) X(i), X(i + 1), X(i + 2), X(i + 3), X(i + 4), X(i + 5), X(i + 6), X(i + 7)
+#define X64(i) X8(i), X8(i + 8), X8(i + 16), X8(i + 24), X8(i + 32), X8(i + 40), X8(i + 48), X8(i + 56)
+    X64(0), X64(64), X64(128), X64(192)
+#undef X64
+#undef X8
+#undef X
+};
+
+__global__ __launch_bounds__(256) void expand_keys_kernel(const uint8_t *__restrict__ keys,
+                                                          uint32_t key_bytes, uint64_t nkeys,
+                                                          aes_key_schedule_t *__restrict__ out)
+{
+    __shared__ uint8_t sbox[256];
+    for (uint32_t i = threadIdx.x; i < 256u; i += blockDim.x)
+        sbox[i] = g_sbox[i];
+    __syncthreads();
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nkeys)
+        return;
+    uint8_t key[32];
+    for (uint32_t i = 0; i < key_bytes; ++i)
+        key[i] = keys[k * key_bytes + i];
+    aes_key_schedule_t ks;
+    expand_schedule(key, key_bytes, &ks, sbox);
+    out[k] = ks;
+}
+
+}  // namespace
+
+hipError_t expand_keys_device(const uint8_t *keys, uint32_t key_bytes, uint64_t nkeys,
+                              aes_key_schedule_t *ks, hipStream_t stream)
+{
+    const uint32_t wg = 256;
+    const uint64_t grid = (nkeys + wg - 1) / wg;
+    if (grid > 0x7fffffffull)
+        return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(expand_keys_kernel, dim3((uint32_t)grid), dim3(wg), 0, stream, keys,
+                       key_bytes, nkeys, ks);
+    return hipGetLastError();
+}
+
+}  // namespace aesmi

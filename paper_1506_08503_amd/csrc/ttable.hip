@@ -1,0 +1,471 @@
+// ttable.hip -- AES round function as LDS table lookups (gfx950).
+//
+// One round of the cipher (sec. II: SubBytes, ShiftRows, MixColumns,
+// AddRoundKey) maps the four state columns s_0..s_3 (little-endian words,
+// byte j = row j) to
+//     s'_c = T0[s_c.b0] ^ T1[s_{c+1}.b1] ^ T2[s_{c+2}.b2] ^ T3[s_{c+3}.b3] ^ k_c
+// where Tj[x] is column j of the mix matrix circ[2 3 1 1] (App. A1) times S(x):
+// the S-box lookup and the GF(2^8) matrix product of the paper folded into one
+// 256-entry table per row.  The last round (no MixColumns, App. A1) takes the
+// S-box byte out of the same tables.  Decryption is the equivalent inverse
+// cipher with circ[14 11 13 9] (App. A4) tables and an inverse S-box table.
+//
+// LDS layout (bank-conflict free, 32 copies): copy (lane & 31) of entry x of
+// table t sits at byte
+//     (t >> 1) << 16 | x << 8 | (t & 1) << 7 | (lane & 31) << 2
+// so 32 consecutive lanes always touch 32 distinct banks whatever their bytes,
+// and a single v_perm_b32 builds the address from the state word and a
+// per-lane constant.  Four encryption tables take 128 KiB; decryption adds a
+// 32-copy inverse S-box (32 KiB) at 0x20000: 160 KiB, the whole LDS of a CU.
+//
+// Work split: each lane carries `bpl` independent blocks per iteration
+// (instruction-level parallelism for the LDS latency); a wave touches 64
+// consecutive 16-byte blocks per load (1 KiB, one global_load_dwordx4 per
+// lane); workgroups stride over the buffer (persistent grid, one workgroup per
+// CU because of the LDS footprint).
+#include <hip/hip_runtime.h>
+
+#include "aes_tables.hpp"
+#include "internal.hpp"
+
+namespace aesmi {
+namespace {
+
+__constant__ Tables g_tab = kTables;
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr uint32_t kEncLdsBytes = 4u * 256u * 32u * 4u;          // 131072
+constexpr uint32_t kSiBase = 0x20000u;
+constexpr uint32_t kDecLdsBytes = kEncLdsBytes + 256u * 32u * 4u;  // 163840
+
+__device__ __forceinline__ uint32_t lds_word(const char *lds, uint32_t byte_addr)
+{
+    return *reinterpret_cast<const uint32_t *>(lds + byte_addr);
+}
+
+// Per-lane address constant of table t: bytes 0 and 2 of the LDS address.
+__device__ __forceinline__ uint32_t lane_const(uint32_t t, uint32_t lane)
+{
+    return ((t >> 1) << 16) | ((t & 1u) << 7) | ((lane & 31u) << 2);
+}
+
+// Address of entry (byte k of w) in table t: byte k of w goes to address byte
+// 1, the lane constant supplies bytes 0 and 2, byte 3 is zero.
+template <int K>
+__device__ __forceinline__ uint32_t taddr(uint32_t w, uint32_t lc)
+{
+    return __builtin_amdgcn_perm(w, lc, 0x0c020000u | ((4u + K) << 8));
+}
+
+struct Lc {
+    uint32_t t[4];
+};
+
+__device__ __forceinline__ Lc make_lc(uint32_t lane)
+{
+    Lc lc;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        lc.t[t] = lane_const(t, lane);
+    return lc;
+}
+
+#define TL(T, W, K) lds_word(lds, taddr<K>((W), lc.t[T]))
+
+// Three-input XOR in one VALU op (gfx950 v_bitop3_b32, truth table 0x96);
+// gfx9 has no v_xor3_b32.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// (a | b) ^ c in one op (truth table 0x56).
+__device__ __forceinline__ uint32_t or_xor(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x56);
+}
+
+// One output column of a table round: t0 ^ t1 ^ t2 ^ t3 ^ k in two ops.
+__device__ __forceinline__ uint32_t col5(uint32_t t0, uint32_t t1, uint32_t t2, uint32_t t3,
+                                         uint32_t k)
+{
+    return xor3(xor3(t0, t1, t2), t3, k);
+}
+
+// ---------------------------------------------------------------- tables
+// Fill the four encryption tables (rotations of te0) into LDS.  Thread tid
+// takes table tid / 256, entry tid % 256 (for wg < 1024 it loops) and writes
+// its 32 copies as 8 x 16-byte stores.
+__device__ void fill_tables(char *lds, bool decrypt)
+{
+    const uint32_t nthreads = blockDim.x;
+    for (uint32_t e = threadIdx.x; e < 1024u; e += nthreads) {
+        const uint32_t t = e >> 8, x = e & 255u;
+        uint32_t base = decrypt ? g_tab.td0[x] : g_tab.te0[x];
+        uint32_t v = t ? ((base << (8 * t)) | (base >> (32 - 8 * t))) : base;
+        uint32_t addr = ((t >> 1) << 16) | (x << 8) | ((t & 1u) << 7);
+        u32x4 q = {v, v, v, v};
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            *reinterpret_cast<u32x4 *>(lds + addr + 16 * c) = q;
+    }
+    if (decrypt) {
+        for (uint32_t x = threadIdx.x; x < 256u; x += nthreads) {
+            uint32_t v = 0x01010101u * g_tab.inv_sbox[x];
+            u32x4 q = {v, v, v, v};
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                *reinterpret_cast<u32x4 *>(lds + kSiBase + (x << 7) + 16 * c) = q;
+        }
+    }
+}
+
+// ------------------------------------------------------------ encryption
+// One middle round on one block, round key words rk[0..3].
+__device__ __forceinline__ void enc_round(uint32_t (&s)[4], const uint32_t *rk,
+                                          const char *lds, const Lc &lc)
+{
+    uint32_t n0 = col5(TL(0, s[0], 0), TL(1, s[1], 1), TL(2, s[2], 2), TL(3, s[3], 3), rk[0]);
+    uint32_t n1 = col5(TL(0, s[1], 0), TL(1, s[2], 1), TL(2, s[3], 2), TL(3, s[0], 3), rk[1]);
+    uint32_t n2 = col5(TL(0, s[2], 0), TL(1, s[3], 1), TL(2, s[0], 2), TL(3, s[1], 3), rk[2]);
+    uint32_t n3 = col5(TL(0, s[3], 0), TL(1, s[0], 1), TL(2, s[1], 2), TL(3, s[2], 3), rk[3]);
+    s[0] = n0;
+    s[1] = n1;
+    s[2] = n2;
+    s[3] = n3;
+}
+
+// Last round: S-box bytes only.  T3 holds S(x) in byte 0, T0 in byte 1, T1 in
+// byte 2 and T2 in byte 3.
+__device__ __forceinline__ uint32_t enc_last_col(uint32_t a, uint32_t b, uint32_t c,
+                                                 uint32_t d, uint32_t k, const char *lds,
+                                                 const Lc &lc)
+{
+    uint32_t lo = __builtin_amdgcn_perm(TL(0, b, 1), TL(3, a, 0), 0x0c0c0500u);
+    uint32_t hi = __builtin_amdgcn_perm(TL(2, d, 3), TL(1, c, 2), 0x07020c0cu);
+    return or_xor(lo, hi, k);
+}
+
+__device__ __forceinline__ void enc_last(uint32_t (&s)[4], const uint32_t *rk,
+                                         const char *lds, const Lc &lc)
+{
+    uint32_t n0 = enc_last_col(s[0], s[1], s[2], s[3], rk[0], lds, lc);
+    uint32_t n1 = enc_last_col(s[1], s[2], s[3], s[0], rk[1], lds, lc);
+    uint32_t n2 = enc_last_col(s[2], s[3], s[0], s[1], rk[2], lds, lc);
+    uint32_t n3 = enc_last_col(s[3], s[0], s[1], s[2], rk[3], lds, lc);
+    s[0] = n0;
+    s[1] = n1;
+    s[2] = n2;
+    s[3] = n3;
+}
+
+template <int NR, int FIRST, int BPL>
+__device__ __forceinline__ void enc_rounds(uint32_t (&s)[BPL][4], const uint32_t *rk,
+                                           const char *lds, const Lc &lc)
+{
+#pragma unroll
+    for (int r = FIRST; r < NR; ++r) {
+#pragma unroll
+        for (int b = 0; b < BPL; ++b)
+            enc_round(s[b], rk + 4 * r, lds, lc);
+    }
+#pragma unroll
+    for (int b = 0; b < BPL; ++b)
+        enc_last(s[b], rk + 4 * NR, lds, lc);
+}
+
+// ------------------------------------------------------------ decryption
+__device__ __forceinline__ void dec_round(uint32_t (&s)[4], const uint32_t *rk,
+                                          const char *lds, const Lc &lc)
+{
+    uint32_t n0 = col5(TL(0, s[0], 0), TL(1, s[3], 1), TL(2, s[2], 2), TL(3, s[1], 3), rk[0]);
+    uint32_t n1 = col5(TL(0, s[1], 0), TL(1, s[0], 1), TL(2, s[3], 2), TL(3, s[2], 3), rk[1]);
+    uint32_t n2 = col5(TL(0, s[2], 0), TL(1, s[1], 1), TL(2, s[0], 2), TL(3, s[3], 3), rk[2]);
+    uint32_t n3 = col5(TL(0, s[3], 0), TL(1, s[2], 1), TL(2, s[1], 2), TL(3, s[0], 3), rk[3]);
+    s[0] = n0;
+    s[1] = n1;
+    s[2] = n2;
+    s[3] = n3;
+}
+
+// Inverse S-box word (byte replicated 4x) of byte K of w.
+template <int K>
+__device__ __forceinline__ uint32_t si_word(uint32_t w, const char *lds, uint32_t lcs)
+{
+    return lds_word(lds, (((w >> (8 * K)) & 255u) << 7) | lcs);
+}
+
+__device__ __forceinline__ uint32_t dec_last_col(uint32_t a, uint32_t b, uint32_t c,
+                                                 uint32_t d, uint32_t k, const char *lds,
+                                                 uint32_t lcs)
+{
+    uint32_t lo = __builtin_amdgcn_perm(si_word<1>(b, lds, lcs), si_word<0>(a, lds, lcs),
+                                        0x0c0c0400u);
+    uint32_t hi = __builtin_amdgcn_perm(si_word<3>(d, lds, lcs), si_word<2>(c, lds, lcs),
+                                        0x04000c0cu);
+    return or_xor(lo, hi, k);
+}
+
+template <int NR, int BPL>
+__device__ __forceinline__ void dec_rounds(uint32_t (&s)[BPL][4], const uint32_t *dk,
+                                           const char *lds, const Lc &lc, uint32_t lcs)
+{
+#pragma unroll
+    for (int r = 1; r < NR; ++r) {
+#pragma unroll
+        for (int b = 0; b < BPL; ++b)
+            dec_round(s[b], dk + 4 * r, lds, lc);
+    }
+#pragma unroll
+    for (int b = 0; b < BPL; ++b) {
+        const uint32_t *k = dk + 4 * NR;
+        uint32_t n0 = dec_last_col(s[b][0], s[b][3], s[b][2], s[b][1], k[0], lds, lcs);
+        uint32_t n1 = dec_last_col(s[b][1], s[b][0], s[b][3], s[b][2], k[1], lds, lcs);
+        uint32_t n2 = dec_last_col(s[b][2], s[b][1], s[b][0], s[b][3], k[2], lds, lcs);
+        uint32_t n3 = dec_last_col(s[b][3], s[b][2], s[b][1], s[b][0], k[3], lds, lcs);
+        s[b][0] = n0;
+        s[b][1] = n1;
+        s[b][2] = n2;
+        s[b][3] = n3;
+    }
+}
+
+// ------------------------------------------------------------- ECB body
+// Blocks [0, nblocks) are split into tiles of wg * BPL blocks; whole tiles go
+// round-robin over the workgroups with no bounds checks inside (so the BPL
+// blocks of a lane stay interleaved), the remainder one block per lane.
+template <int NR, bool DEC, int BPL>
+__device__ __forceinline__ void ecb_blocks(const uint32_t *rk, const u32x4 *__restrict__ in,
+                                           u32x4 *__restrict__ out, uint64_t first,
+                                           uint64_t stride, const char *lds, const Lc &lc,
+                                           uint32_t lcs)
+{
+    uint32_t s[BPL][4];
+#pragma unroll
+    for (int b = 0; b < BPL; ++b) {
+        u32x4 v = __builtin_nontemporal_load(in + first + b * stride);
+        s[b][0] = v.x ^ rk[0];
+        s[b][1] = v.y ^ rk[1];
+        s[b][2] = v.z ^ rk[2];
+        s[b][3] = v.w ^ rk[3];
+    }
+    if (DEC)
+        dec_rounds<NR, BPL>(s, rk, lds, lc, lcs);
+    else
+        enc_rounds<NR, 1, BPL>(s, rk, lds, lc);
+#pragma unroll
+    for (int b = 0; b < BPL; ++b)
+        __builtin_nontemporal_store(u32x4{s[b][0], s[b][1], s[b][2], s[b][3]},
+                                    out + first + b * stride);
+}
+
+template <int NR, bool DEC, int BPL>
+__device__ void ecb_body(const aes_key_schedule_t *__restrict__ ks,
+                         const u32x4 *__restrict__ in, u32x4 *__restrict__ out,
+                         uint64_t nblocks, const char *lds, const Lc &lc, uint32_t lcs)
+{
+    const uint32_t *rk = DEC ? ks->rk_dec : ks->rk_enc;
+    const uint64_t wg = blockDim.x;
+    const uint64_t tile = wg * BPL;
+    const uint64_t ntiles = nblocks / tile;
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
+        ecb_blocks<NR, DEC, BPL>(rk, in, out, t * tile + threadIdx.x, wg, lds, lc, lcs);
+    for (uint64_t i = ntiles * tile + (uint64_t)blockIdx.x * wg + threadIdx.x; i < nblocks;
+         i += (uint64_t)gridDim.x * wg)
+        ecb_blocks<NR, DEC, 1>(rk, in, out, i, 0, lds, lc, lcs);
+}
+
+template <bool DEC, int BPL>
+__global__ __launch_bounds__(1024) void ecb_ttable_kernel(
+    const aes_key_schedule_t *__restrict__ ks, const u32x4 *__restrict__ in,
+    u32x4 *__restrict__ out, uint64_t nblocks)
+{
+    __shared__ __attribute__((aligned(16))) char lds[DEC ? kDecLdsBytes : kEncLdsBytes];
+    fill_tables(lds, DEC);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const Lc lc = make_lc(lane);
+    const uint32_t lcs = kSiBase | ((lane & 31u) << 2);
+    switch (ks->nr) {
+    case 10: ecb_body<10, DEC, BPL>(ks, in, out, nblocks, lds, lc, lcs); break;
+    case 12: ecb_body<12, DEC, BPL>(ks, in, out, nblocks, lds, lc, lcs); break;
+    case 14: ecb_body<14, DEC, BPL>(ks, in, out, nblocks, lds, lc, lcs); break;
+    default: break;   // not a schedule made by this library: leave out untouched
+    }
+}
+
+// ------------------------------------------------------------- CTR body
+__device__ __forceinline__ uint32_t bswap32(uint32_t x)
+{
+    return __builtin_amdgcn_perm(x, x, 0x00010203u);
+}
+
+// Counter block i: nonce words n0..n2 and the big-endian counter (ctr0 + i)
+// as column 3.  Columns 0..2 are the same for every block, so the three
+// round-1 lookups each output column takes from them are done once per
+// thread (P0..P3 below); per block only the four lookups that read column 3
+// remain in round 1.  The result is the same cipher, bit for bit.
+template <int NR, int BPL>
+__device__ __forceinline__ void ctr_blocks(const uint32_t *rk, const u32x4 *__restrict__ in,
+                                           u32x4 *__restrict__ out, uint64_t first,
+                                           uint64_t stride, uint32_t ctr0, uint32_t p0,
+                                           uint32_t p1, uint32_t p2, uint32_t p3,
+                                           const char *lds, const Lc &lc)
+{
+    uint32_t s[BPL][4];
+    u32x4 x[BPL];
+#pragma unroll
+    for (int b = 0; b < BPL; ++b) {
+        const uint64_t i = first + b * stride;
+        x[b] = __builtin_nontemporal_load(in + i);
+        const uint32_t w3 = bswap32(ctr0 + (uint32_t)i) ^ rk[3];
+        s[b][0] = p0 ^ TL(3, w3, 3);
+        s[b][1] = p1 ^ TL(2, w3, 2);
+        s[b][2] = p2 ^ TL(1, w3, 1);
+        s[b][3] = p3 ^ TL(0, w3, 0);
+    }
+    enc_rounds<NR, 2, BPL>(s, rk, lds, lc);
+#pragma unroll
+    for (int b = 0; b < BPL; ++b)
+        __builtin_nontemporal_store(u32x4{x[b].x ^ s[b][0], x[b].y ^ s[b][1],
+                                          x[b].z ^ s[b][2], x[b].w ^ s[b][3]},
+                                    out + first + b * stride);
+}
+
+template <int NR, int BPL>
+__device__ void ctr_body(const aes_key_schedule_t *__restrict__ ks,
+                         const u32x4 *__restrict__ in, u32x4 *__restrict__ out,
+                         uint64_t nbytes, uint32_t n0, uint32_t n1, uint32_t n2,
+                         uint32_t ctr0, const char *lds, const Lc &lc)
+{
+    const uint32_t *rk = ks->rk_enc;
+    const uint32_t u0 = n0 ^ rk[0], u1 = n1 ^ rk[1], u2 = n2 ^ rk[2];
+    const uint32_t p0 = xor3(TL(0, u0, 0), TL(1, u1, 1), TL(2, u2, 2)) ^ rk[4];
+    const uint32_t p1 = xor3(TL(0, u1, 0), TL(1, u2, 1), TL(3, u0, 3)) ^ rk[5];
+    const uint32_t p2 = xor3(TL(0, u2, 0), TL(2, u0, 2), TL(3, u1, 3)) ^ rk[6];
+    const uint32_t p3 = xor3(TL(1, u0, 1), TL(2, u1, 2), TL(3, u2, 3)) ^ rk[7];
+
+    const uint64_t nfull = nbytes >> 4;
+    const uint64_t wg = blockDim.x;
+    const uint64_t tile = wg * BPL;
+    const uint64_t ntiles = nfull / tile;
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
+        ctr_blocks<NR, BPL>(rk, in, out, t * tile + threadIdx.x, wg, ctr0, p0, p1, p2, p3,
+                            lds, lc);
+    for (uint64_t i = ntiles * tile + (uint64_t)blockIdx.x * wg + threadIdx.x; i < nfull;
+         i += (uint64_t)gridDim.x * wg)
+        ctr_blocks<NR, 1>(rk, in, out, i, 0, ctr0, p0, p1, p2, p3, lds, lc);
+
+    // Ragged tail: the first (nbytes % 16) bytes of block nfull.
+    const uint32_t tail = (uint32_t)(nbytes & 15u);
+    if (tail && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        uint32_t s1[1][4] = {{u0, u1, u2, bswap32(ctr0 + (uint32_t)nfull) ^ rk[3]}};
+        enc_rounds<NR, 1, 1>(s1, rk, lds, lc);
+        const uint8_t *src = reinterpret_cast<const uint8_t *>(in + nfull);
+        uint8_t *dst = reinterpret_cast<uint8_t *>(out + nfull);
+        for (uint32_t k = 0; k < tail; ++k)
+            dst[k] = src[k] ^ (uint8_t)(s1[0][k >> 2] >> (8 * (k & 3u)));
+    }
+}
+
+template <int BPL>
+__global__ __launch_bounds__(1024) void ctr_ttable_kernel(
+    const aes_key_schedule_t *__restrict__ ks, const u32x4 *__restrict__ in,
+    u32x4 *__restrict__ out, uint64_t nbytes, uint32_t n0, uint32_t n1, uint32_t n2,
+    uint32_t ctr0)
+{
+    __shared__ __attribute__((aligned(16))) char lds[kEncLdsBytes];
+    fill_tables(lds, false);
+    __syncthreads();
+    const Lc lc = make_lc(threadIdx.x & 63u);
+    switch (ks->nr) {
+    case 10: ctr_body<10, BPL>(ks, in, out, nbytes, n0, n1, n2, ctr0, lds, lc); break;
+    case 12: ctr_body<12, BPL>(ks, in, out, nbytes, n0, n1, n2, ctr0, lds, lc); break;
+    case 14: ctr_body<14, BPL>(ks, in, out, nbytes, n0, n1, n2, ctr0, lds, lc); break;
+    default: break;
+    }
+}
+
+// ------------------------------------------------------------- launching
+Shape resolve(const aes_launch_t *launch, uint64_t nblocks)
+{
+    Shape sh{1024, 0, 2};
+    const int cu = device_cu_count() > 0 ? device_cu_count() : 256;
+    uint32_t per_cu = 1;
+    if (launch) {
+        if (launch->wg_size)
+            sh.wg = launch->wg_size;
+        if (launch->blocks_per_lane)
+            sh.bpl = launch->blocks_per_lane;
+        if (launch->grid_per_cu)
+            per_cu = launch->grid_per_cu;
+    }
+    if (!launch || !launch->wg_size) {
+        // Small inputs: narrower workgroups so that every CU gets work.
+        while (sh.wg > 256 && (nblocks + sh.wg * sh.bpl - 1) / (sh.wg * sh.bpl) < (uint64_t)cu)
+            sh.wg >>= 1;
+        if (!launch || !launch->blocks_per_lane)
+            if ((nblocks + sh.wg * sh.bpl - 1) / (sh.wg * sh.bpl) < (uint64_t)cu)
+                sh.bpl = 1;
+    }
+    uint64_t need = (nblocks + (uint64_t)sh.wg * sh.bpl - 1) / ((uint64_t)sh.wg * sh.bpl);
+    uint64_t cap = (uint64_t)cu * per_cu;
+    sh.grid = (uint32_t)(need < cap ? (need ? need : 1) : cap);
+    return sh;
+}
+
+bool valid_shape(const Shape &sh)
+{
+    return sh.wg >= 64 && sh.wg <= 1024 && sh.wg % 64 == 0 &&
+           (sh.bpl == 1 || sh.bpl == 2 || sh.bpl == 4) && sh.grid >= 1;
+}
+
+}  // namespace
+
+hipError_t ttable_ecb(bool decrypt, const aes_key_schedule_t *ks, const void *in,
+                      void *out, uint64_t nblocks, const aes_launch_t *launch,
+                      hipStream_t stream)
+{
+    Shape sh = resolve(launch, nblocks);
+    if (!valid_shape(sh))
+        return hipErrorInvalidConfiguration;
+    const u32x4 *src = static_cast<const u32x4 *>(in);
+    u32x4 *dst = static_cast<u32x4 *>(out);
+#define LAUNCH_ECB(D, B)                                                                \
+    hipLaunchKernelGGL((ecb_ttable_kernel<D, B>), dim3(sh.grid), dim3(sh.wg), 0, stream, \
+                       ks, src, dst, nblocks)
+    if (decrypt) {
+        if (sh.bpl == 1) LAUNCH_ECB(true, 1);
+        else if (sh.bpl == 2) LAUNCH_ECB(true, 2);
+        else LAUNCH_ECB(true, 4);
+    } else {
+        if (sh.bpl == 1) LAUNCH_ECB(false, 1);
+        else if (sh.bpl == 2) LAUNCH_ECB(false, 2);
+        else LAUNCH_ECB(false, 4);
+    }
+#undef LAUNCH_ECB
+    return hipGetLastError();
+}
+
+hipError_t ttable_ctr(const aes_key_schedule_t *ks, const uint32_t nonce_words[3],
+                      uint32_t ctr0, const void *in, void *out, uint64_t nbytes,
+                      const aes_launch_t *launch, hipStream_t stream)
+{
+    Shape sh = resolve(launch, (nbytes + 15) / 16);
+    if (!valid_shape(sh))
+        return hipErrorInvalidConfiguration;
+    const u32x4 *src = static_cast<const u32x4 *>(in);
+    u32x4 *dst = static_cast<u32x4 *>(out);
+#define LAUNCH_CTR(B)                                                                    \
+    hipLaunchKernelGGL((ctr_ttable_kernel<B>), dim3(sh.grid), dim3(sh.wg), 0, stream, ks, \
+                       src, dst, nbytes, nonce_words[0], nonce_words[1], nonce_words[2],  \
+                       ctr0)
+    if (sh.bpl == 1) LAUNCH_CTR(1);
+    else if (sh.bpl == 2) LAUNCH_CTR(2);
+    else LAUNCH_CTR(4);
+#undef LAUNCH_CTR
+    return hipGetLastError();
+}
+
+}  // namespace aesmi

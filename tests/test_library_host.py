@@ -1,0 +1,139 @@
+"""The C-ABI library on the host: symbols, host key expansion, argument checks.
+
+No GPU needed: every call here either is pure host code (aes_expand_key,
+aes_status_string, aes_batched_workspace_bytes) or fails argument validation,
+which the library does before any HIP call.
+"""
+import ctypes
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1506_08503_amd as am
+
+L = am.lib()
+VP = ctypes.c_void_p
+
+
+def test_every_header_function_is_exported():
+    names = am.header_functions()
+    assert "aes_ctr_xcrypt" in names and len(names) >= 15
+    out = subprocess.run(["nm", "-D", "--defined-only", am.aesmi.LIB_PATH],
+                         stdout=subprocess.PIPE, text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(L, n)
+
+
+def _words_to_bytes(words, n):
+    return np.array(words[:n], dtype="<u4").view(np.uint8)
+
+
+@pytest.mark.parametrize("key_bytes", [16, 24, 32])
+def test_host_key_schedule_matches_oracle(oracle, key_bytes):
+    g = np.random.Generator(np.random.PCG64(key_bytes))
+    keys = [g.bytes(key_bytes) for _ in range(20)] + [b"\xff" * key_bytes,
+                                                     b"\x00" * key_bytes]
+    for key in keys:
+        ks = am.expand_key(key)
+        nr, rk = oracle.expand_key(key)
+        assert ks.nr == nr and ks.key_bytes == key_bytes
+        enc = _words_to_bytes(list(ks.rk_enc), 4 * (nr + 1))
+        assert np.array_equal(enc, rk)
+        # equivalent inverse cipher keys: reversed, InvMixColumns on inner keys
+        dec = _words_to_bytes(list(ks.rk_dec), 4 * (nr + 1)).reshape(nr + 1, 16)
+        rkr = rk.reshape(nr + 1, 16)
+        assert np.array_equal(dec[0], rkr[nr]) and np.array_equal(dec[nr], rkr[0])
+        for r in range(1, nr):
+            assert np.array_equal(dec[r], oracle.inv_mix_columns(rkr[nr - r]))
+        assert all(w == 0 for w in list(ks.rk_enc)[4 * (nr + 1):])
+
+
+def _status(fn, *args):
+    return fn(*args)
+
+
+def test_expand_key_errors():
+    ks = am.KeySchedule()
+    assert L.aes_expand_key(None, 16, ctypes.byref(ks)) == -1
+    buf = ctypes.create_string_buffer(32)
+    for bad in (0, 8, 15, 17, 20, 31, 33, 64):
+        assert L.aes_expand_key(buf, bad, ctypes.byref(ks)) == -2
+    with pytest.raises(am.AesError, match="AES_ERR_KEYLEN"):
+        am.expand_key(b"x" * 15)
+    assert L.aes_expand_keys_device(VP(0x1000), 17, 4, VP(0x2000), None) == -2
+    assert L.aes_expand_keys_device(VP(0x1000), 16, 0, None, None) == 0
+    assert L.aes_expand_keys_device(None, 16, 3, VP(0x2000), None) == -1
+
+
+def test_ecb_validation():
+    ks, a, b = VP(0x10000), VP(0x20000), VP(0x40000)
+    for fn in (L.aes_ecb_encrypt, L.aes_ecb_decrypt):
+        assert fn(None, None, None, 0, None) == 0              # empty: no-op
+        assert fn(None, a, b, 16, None) == -1
+        assert fn(ks, None, b, 16, None) == -1
+        assert fn(ks, a, None, 16, None) == -1
+        assert fn(ks, a, b, 17, None) == -3
+        assert fn(ks, VP(0x20008), b, 32, None) == -4
+        assert fn(ks, a, VP(0x40004), 32, None) == -4
+        assert fn(ks, a, VP(0x20010), 64, None) == -5            # partial overlap
+        assert fn(ks, VP(0x20010), a, 64, None) == -5
+    bad = am.Launch(0, 100, 0, 0)
+    assert L.aes_ecb_encrypt_ex(ks, a, b, 32, ctypes.byref(bad), None) == -9
+    bad = am.Launch(7, 0, 0, 0)
+    assert L.aes_ecb_decrypt_ex(ks, a, b, 32, ctypes.byref(bad), None) == -9
+    bad = am.Launch(1, 256, 0, 3)
+    assert L.aes_ecb_encrypt_ex(ks, a, b, 32, ctypes.byref(bad), None) == -9
+
+
+def test_ctr_validation():
+    ks, a, b = VP(0x10000), VP(0x20000), VP(0x40000)
+    nonce = ctypes.create_string_buffer(12)
+    f = L.aes_ctr_xcrypt
+    assert f(None, None, 0, None, None, 0, None) == 0
+    assert f(ks, None, 0, a, b, 5, None) == -1
+    assert f(None, nonce, 0, a, b, 5, None) == -1
+    assert f(ks, nonce, 0, VP(0x20001), b, 5, None) == -4
+    assert f(ks, nonce, 0, a, VP(0x20008), 64, None) == -4
+    assert f(ks, nonce, 0, a, VP(0x20010), 64, None) == -5
+    # counter space: ctr0 + ceil(n / 16) must stay <= 2^32
+    assert f(ks, nonce, 2 ** 32 - 1, a, b, 17, None) == -6
+    assert f(ks, nonce, 2 ** 32 - 2, a, b, 33, None) == -6
+    bad = am.Launch(0, 2048, 0, 0)
+    assert L.aes_ctr_xcrypt_ex(ks, nonce, 0, a, b, 16, ctypes.byref(bad), None) == -9
+    # status strings
+    for code, name in am.STATUS.items():
+        assert L.aes_status_string(code)
+    assert L.aes_status_string(12345) == b"unknown status"
+
+
+def test_batched_validation():
+    segs, kt, a, b, ws = VP(0x10000), VP(0x20000), VP(0x40000), VP(0x80000), VP(0x100000)
+    f = L.aes_ctr_xcrypt_batched
+    need = L.aes_batched_workspace_bytes(10)
+    assert need >= 256 and L.aes_batched_workspace_bytes(1000) > need
+    assert f(None, 0, None, 0, None, None, None, None, 0, None) == 0
+    assert f(None, 10, kt, 4, a, b, None, ws, need, None) == -1
+    assert f(segs, 10, kt, 0, a, b, None, ws, need, None) == -7
+    assert f(segs, 10, kt, 4, a, b, None, VP(0x100010), need, None) == -4
+    assert f(segs, 10, kt, 4, a, b, None, ws, need - 1, None) == -9
+    bad = am.BatchTune(0, 0, 0, 100)
+    assert f(segs, 10, kt, 4, a, b, ctypes.byref(bad), ws, need, None) == -9
+    st = ctypes.c_int32(0)
+    assert L.aes_batched_read_status(None, None, ctypes.byref(st)) == -1
+    g = VP()
+    assert L.aes_batched_graph_create(segs, 10, kt, 4, a, b, None, ws, 1, None, None) == -1
+    assert L.aes_batched_graph_destroy(None) == 0
+    assert L.aes_batched_graph_launch(None, None) == -1
+
+
+def test_binding_rejects_cpu_tensors():
+    import torch
+    x = torch.zeros(32, dtype=torch.uint8)
+    with pytest.raises(TypeError):
+        am.ctr_xcrypt(x, b"n" * 12, 0, x)
+    with pytest.raises(TypeError):
+        am.ecb_encrypt(x, x)
