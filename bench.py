@@ -39,6 +39,9 @@ def parse():
     p.add_argument("--nbytes", type=int, default=4 << 30)
     p.add_argument("--layout", choices=["auto", "ttable", "bitslice"], default="auto")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--mode", choices=["aes", "copy"], default="aes",
+                   help="copy: time a plain device copy of the same buffer instead "
+                        "(reference for HBM counter calibration)")
     p.add_argument("--cpu-threads", type=int, default=0)
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     return p.parse_args()
@@ -92,7 +95,10 @@ def main():
     kw = {} if layout == am.LAYOUT_AUTO else {"layout": layout}
 
     def step():
-        am.ctr_xcrypt(ks, inp.nonce, inp.ctr0, x, out=y, **kw)
+        if args.mode == "copy":
+            y.copy_(x)
+        else:
+            am.ctr_xcrypt(ks, inp.nonce, inp.ctr0, x, out=y, **kw)
 
     for _ in range(args.warmup):
         step()
@@ -129,6 +135,11 @@ def main():
         roofline["lds_treads_per_s"] = round(lds_reads / (avg_ms * 1e-3) / 1e12, 3)
         roofline["lds_frac_at_2p4ghz"] = round(lds_reads / (avg_ms * 1e-3) / 1e12
                                                / LDS_PEAK_TREADS, 4)
+    if args.mode == "copy":
+        print(json.dumps({"mode": "copy", "nbytes": inp.nbytes, "ms_avg": round(avg_ms, 4),
+                          "GBps_read_plus_write": round(2 * inp.nbytes / (avg_ms * 1e-3) / 1e9,
+                                                        1)}), flush=True)
+        return
     out = {"metric": "AES-128-CTR GB/s at 4 GiB", "value": round(value, 2), "unit": "GB/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,

@@ -369,6 +369,132 @@ __device__ void ctr_body(const aes_key_schedule_t *__restrict__ ks,
     }
 }
 
+// Counter groups.  Write the counter of block i as c = ctr0 + i and let the
+// blocks of one wave be the 256 counters sharing c >> 8 (four per lane, lane
+// l taking low bytes l, l + 64, l + 128, l + 192).  After the initial key
+// addition only column 3 of a counter block depends on c, and round 1 reads
+// one byte of it per output column:
+//   * output column 0 reads the low counter byte only, so it depends on
+//     (lane, slot) and on nothing else;
+//   * output columns 1..3 read the upper three counter bytes, which are the
+//     same for the whole group.
+// Round 2 reads one byte of round-1 column 0 per output column, the other
+// three bytes coming from columns 1..3; so round-2 output column c is
+//     Q_c(group) ^ R_c(lane, slot).
+// R is computed once per thread (16 lookups), Q once per group and wave (15
+// lookups shared by 256 blocks), and each block starts at round 3: 16 * (Nr-2)
+// lookups instead of 16 * Nr - 12.  Same cipher, bit for bit.
+template <int NR>
+__device__ __forceinline__ void ctr_group(const uint32_t *rk, const u32x4 *__restrict__ in,
+                                          u32x4 *__restrict__ out, uint64_t first, uint32_t cg,
+                                          const uint32_t (&pre)[4], const uint32_t (&r2)[4][4],
+                                          const char *lds, const Lc &lc)
+{
+    // group constants (all lanes compute the same values)
+    const uint32_t w3 = bswap32(cg) ^ rk[3];
+    const uint32_t s1 = pre[1] ^ TL(2, w3, 2);
+    const uint32_t s2 = pre[2] ^ TL(1, w3, 1);
+    const uint32_t s3 = pre[3] ^ TL(0, w3, 0);
+    const uint32_t q0 = xor3(TL(1, s1, 1), TL(2, s2, 2), TL(3, s3, 3)) ^ rk[8];
+    const uint32_t q1 = xor3(TL(0, s1, 0), TL(1, s2, 1), TL(2, s3, 2)) ^ rk[9];
+    const uint32_t q2 = xor3(TL(0, s2, 0), TL(1, s3, 1), TL(3, s1, 3)) ^ rk[10];
+    const uint32_t q3 = xor3(TL(0, s3, 0), TL(2, s1, 2), TL(3, s2, 3)) ^ rk[11];
+    uint32_t s[4][4];
+    u32x4 x[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        x[b] = __builtin_nontemporal_load(in + first + 64 * b);
+        s[b][0] = q0 ^ r2[b][0];
+        s[b][1] = q1 ^ r2[b][1];
+        s[b][2] = q2 ^ r2[b][2];
+        s[b][3] = q3 ^ r2[b][3];
+    }
+    enc_rounds<NR, 3, 4>(s, rk, lds, lc);
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        __builtin_nontemporal_store(u32x4{x[b].x ^ s[b][0], x[b].y ^ s[b][1],
+                                          x[b].z ^ s[b][2], x[b].w ^ s[b][3]},
+                                    out + first + 64 * b);
+}
+
+template <int NR>
+__device__ void ctr_body_grouped(const aes_key_schedule_t *__restrict__ ks,
+                                 const u32x4 *__restrict__ in, u32x4 *__restrict__ out,
+                                 uint64_t nbytes, uint32_t n0, uint32_t n1, uint32_t n2,
+                                 uint32_t ctr0, const char *lds, const Lc &lc)
+{
+    const uint32_t *rk = ks->rk_enc;
+    const uint32_t u0 = n0 ^ rk[0], u1 = n1 ^ rk[1], u2 = n2 ^ rk[2];
+    // round-1 terms that come from the nonce columns (see ctr_body)
+    const uint32_t pre[4] = {xor3(TL(0, u0, 0), TL(1, u1, 1), TL(2, u2, 2)) ^ rk[4],
+                             xor3(TL(0, u1, 0), TL(1, u2, 1), TL(3, u0, 3)) ^ rk[5],
+                             xor3(TL(0, u2, 0), TL(2, u0, 2), TL(3, u1, 3)) ^ rk[6],
+                             xor3(TL(1, u0, 1), TL(2, u1, 2), TL(3, u2, 3)) ^ rk[7]};
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t r2[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t lo = lane + 64u * b;                       // low counter byte
+        const uint32_t s0 = pre[0] ^ TL(3, (lo << 24) ^ rk[3], 3);  // round-1 column 0
+        r2[b][0] = TL(0, s0, 0);
+        r2[b][1] = TL(3, s0, 3);
+        r2[b][2] = TL(2, s0, 2);
+        r2[b][3] = TL(1, s0, 1);
+    }
+
+    const uint64_t nfull = nbytes >> 4;
+    const uint32_t delta = ctr0 & 255u;            // position of block 0 in its group
+    const uint32_t cbase = ctr0 - delta;
+    const uint64_t q_first = delta ? 1u : 0u;
+    const uint64_t q_end = (delta + nfull) >> 8;
+    uint64_t i_lo = nfull, i_hi = nfull;           // blocks covered by whole groups
+    if (q_end > q_first) {
+        i_lo = 256u * q_first - delta;
+        i_hi = 256u * q_end - delta;
+        const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+        const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+        for (uint64_t q = q_first + wave; q < q_end; q += waves)
+            ctr_group<NR>(rk, in, out, 256u * q - delta + lane, cbase + (uint32_t)(256u * q),
+                          pre, r2, lds, lc);
+    }
+    // blocks of the partial first and last groups, one per lane
+    const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nedge = i_lo + (nfull - i_hi);
+    const uint32_t p0 = pre[0], p1 = pre[1], p2 = pre[2], p3 = pre[3];
+    for (uint64_t j = tid; j < nedge; j += nthreads) {
+        const uint64_t i = j < i_lo ? j : i_hi + (j - i_lo);
+        ctr_blocks<NR, 1>(rk, in, out, i, 0, ctr0, p0, p1, p2, p3, lds, lc);
+    }
+
+    const uint32_t tail = (uint32_t)(nbytes & 15u);
+    if (tail && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        uint32_t s1[1][4] = {{u0, u1, u2, bswap32(ctr0 + (uint32_t)nfull) ^ rk[3]}};
+        enc_rounds<NR, 1, 1>(s1, rk, lds, lc);
+        const uint8_t *src = reinterpret_cast<const uint8_t *>(in + nfull);
+        uint8_t *dst = reinterpret_cast<uint8_t *>(out + nfull);
+        for (uint32_t k = 0; k < tail; ++k)
+            dst[k] = src[k] ^ (uint8_t)(s1[0][k >> 2] >> (8 * (k & 3u)));
+    }
+}
+
+__global__ __launch_bounds__(1024) void ctr_grouped_kernel(
+    const aes_key_schedule_t *__restrict__ ks, const u32x4 *__restrict__ in,
+    u32x4 *__restrict__ out, uint64_t nbytes, uint32_t n0, uint32_t n1, uint32_t n2,
+    uint32_t ctr0)
+{
+    __shared__ __attribute__((aligned(16))) char lds[kEncLdsBytes];
+    fill_tables(lds, false);
+    __syncthreads();
+    const Lc lc = make_lc(threadIdx.x & 63u);
+    switch (ks->nr) {
+    case 10: ctr_body_grouped<10>(ks, in, out, nbytes, n0, n1, n2, ctr0, lds, lc); break;
+    case 12: ctr_body_grouped<12>(ks, in, out, nbytes, n0, n1, n2, ctr0, lds, lc); break;
+    case 14: ctr_body_grouped<14>(ks, in, out, nbytes, n0, n1, n2, ctr0, lds, lc); break;
+    default: break;
+    }
+}
+
 template <int BPL>
 __global__ __launch_bounds__(1024) void ctr_ttable_kernel(
     const aes_key_schedule_t *__restrict__ ks, const u32x4 *__restrict__ in,
@@ -390,7 +516,9 @@ __global__ __launch_bounds__(1024) void ctr_ttable_kernel(
 // ------------------------------------------------------------- launching
 Shape resolve(const aes_launch_t *launch, uint64_t nblocks)
 {
-    Shape sh{1024, 0, 2};
+    // Default: 1024-thread workgroups (16 waves, the most one CU can hold
+    // next to 128 KiB of tables), four blocks per lane, one workgroup per CU.
+    Shape sh{1024, 0, 4};
     const int cu = device_cu_count() > 0 ? device_cu_count() : 256;
     uint32_t per_cu = 1;
     if (launch) {
@@ -402,12 +530,9 @@ Shape resolve(const aes_launch_t *launch, uint64_t nblocks)
             per_cu = launch->grid_per_cu;
     }
     if (!launch || !launch->wg_size) {
-        // Small inputs: narrower workgroups so that every CU gets work.
+        // Small inputs: narrower workgroups so that more CUs get work.
         while (sh.wg > 256 && (nblocks + sh.wg * sh.bpl - 1) / (sh.wg * sh.bpl) < (uint64_t)cu)
             sh.wg >>= 1;
-        if (!launch || !launch->blocks_per_lane)
-            if ((nblocks + sh.wg * sh.bpl - 1) / (sh.wg * sh.bpl) < (uint64_t)cu)
-                sh.bpl = 1;
     }
     uint64_t need = (nblocks + (uint64_t)sh.wg * sh.bpl - 1) / ((uint64_t)sh.wg * sh.bpl);
     uint64_t cap = (uint64_t)cu * per_cu;
@@ -463,7 +588,9 @@ hipError_t ttable_ctr(const aes_key_schedule_t *ks, const uint32_t nonce_words[3
                        ctr0)
     if (sh.bpl == 1) LAUNCH_CTR(1);
     else if (sh.bpl == 2) LAUNCH_CTR(2);
-    else LAUNCH_CTR(4);
+    else
+        hipLaunchKernelGGL(ctr_grouped_kernel, dim3(sh.grid), dim3(sh.wg), 0, stream, ks, src,
+                           dst, nbytes, nonce_words[0], nonce_words[1], nonce_words[2], ctr0);
 #undef LAUNCH_CTR
     return hipGetLastError();
 }

@@ -137,6 +137,25 @@ def test_counter_edges(oracle, keys):
         am.ctr_xcrypt(ks, nonce, 2 ** 32 - 1, _to_dev(np.zeros(17, np.uint8)))
 
 
+@pytest.mark.parametrize("delta", [0, 1, 128, 255])
+def test_counter_group_alignment(oracle, keys, delta):
+    """The CTR kernel handles whole 256-counter groups and the partial groups
+    at either end separately: every offset of ctr0 inside a group, inputs
+    shorter than one group, exactly one group, and many groups plus a tail."""
+    g = _rng(40 + delta)
+    for key_bytes in (16, 32):
+        key = keys[key_bytes]
+        ks = am.key_schedule(key)
+        nonce = g.bytes(12)
+        ctr0 = (int(g.integers(0, 2 ** 20)) << 8) | delta
+        for nbytes in (16 * 255, 16 * 256, 16 * 257 + 1, 16 * 511, 16 * (256 * 9 + 300) + 15,
+                       16 * (256 * 64 * 3) + 3):
+            pt = np.frombuffer(g.bytes(nbytes), np.uint8)
+            got = am.ctr_xcrypt(ks, nonce, ctr0, _to_dev(pt))
+            assert np.array_equal(_host(got), oracle.ctr_xcrypt(key, nonce, ctr0, pt, threads=8)), \
+                (key_bytes, nbytes)
+
+
 def test_openssl_weak_keys_on_gpu(oracle):
     """Keys whose schedules run 0xff through the S-box."""
     for key in (b"\x00" * 12 + b"\xff" * 4, b"\xff" * 16, b"\xff" * 32):
