@@ -164,6 +164,56 @@ def test_openssl_weak_keys_on_gpu(oracle):
         assert np.array_equal(_host(am.ecb_encrypt(ks, _to_dev(pt))), oracle.ecb_encrypt(key, pt))
 
 
+# ----------------------------------------------------------- bitsliced layout
+BS_SIZES = [1, 16, 17, 16 * 2047 + 5, 16 * 2048, 16 * 2049 + 15, 16 * (2048 * 3 * 64 + 700) + 9]
+
+
+@pytest.mark.parametrize("key_bytes", [16, 24, 32])
+def test_bitslice_ctr(oracle, keys, key_bytes):
+    """Constant-time bitsliced CTR: 32 blocks per lane word, partial batches,
+    ragged tails, counter carries."""
+    g = _rng(300 + key_bytes)
+    key = keys[key_bytes]
+    ks = am.key_schedule(key)
+    for nbytes in BS_SIZES:
+        nonce = g.bytes(12)
+        ctr0 = int(g.integers(0, 2 ** 32 - (nbytes // 16) - 2))
+        pt = np.frombuffer(g.bytes(nbytes), np.uint8)
+        got = am.ctr_xcrypt(ks, nonce, ctr0, _to_dev(pt), layout=am.LAYOUT_BITSLICE)
+        assert np.array_equal(_host(got), oracle.ctr_xcrypt(key, nonce, ctr0, pt, threads=8)), nbytes
+
+
+@pytest.mark.parametrize("key_bytes", [16, 24, 32])
+def test_bitslice_ecb(oracle, keys, key_bytes):
+    g = _rng(400 + key_bytes)
+    key = keys[key_bytes]
+    ks = am.key_schedule(key)
+    for nblocks in (1, 31, 2048, 2049, 2048 * 70 + 3):
+        pt = np.frombuffer(g.bytes(16 * nblocks), np.uint8)
+        ct = am.ecb_encrypt(ks, _to_dev(pt), layout=am.LAYOUT_BITSLICE)
+        ref = oracle.ecb_encrypt(key, pt, threads=8)
+        assert np.array_equal(_host(ct), ref), nblocks
+        back = am.ecb_decrypt(ks, _to_dev(ref), layout=am.LAYOUT_BITSLICE)
+        assert np.array_equal(_host(back), pt), nblocks
+
+
+def test_bitslice_matches_ttable_large(keys):
+    """Both layouts agree on 64 MiB (CTR, ECB both ways) and on launch shapes."""
+    g = _rng(500)
+    x = _to_dev(np.frombuffer(g.bytes(64 << 20), np.uint8))
+    for key_bytes in (16, 32):
+        ks = am.key_schedule(keys[key_bytes])
+        a = am.ctr_xcrypt(ks, b"\x07" * 12, 1234, x, layout=am.LAYOUT_TTABLE)
+        for wg in (64, 256):
+            b = am.ctr_xcrypt(ks, b"\x07" * 12, 1234, x, layout=am.LAYOUT_BITSLICE,
+                              wg_size=wg, grid_per_cu=1)
+            assert torch.equal(a, b)
+        e1 = am.ecb_encrypt(ks, x, layout=am.LAYOUT_TTABLE)
+        e2 = am.ecb_encrypt(ks, x, layout=am.LAYOUT_BITSLICE)
+        assert torch.equal(e1, e2)
+        assert torch.equal(am.ecb_decrypt(ks, e1, layout=am.LAYOUT_BITSLICE), x)
+
+
 # ------------------------------------------------------------ device keys
 @pytest.mark.parametrize("key_bytes", [16, 24, 32])
 def test_device_key_expansion(oracle, key_bytes):
