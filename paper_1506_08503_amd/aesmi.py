@@ -241,5 +241,103 @@ def ctr_xcrypt(ks: torch.Tensor, nonce: bytes, ctr0: int, x: torch.Tensor,
     return out
 
 
+# ------------------------------------------------------------------- batched
+SEGMENT_DTYPE = None
+
+
+def segment_dtype():
+    """numpy dtype with the byte layout of aes_segment_t (48 bytes)."""
+    import numpy as np
+    global SEGMENT_DTYPE
+    if SEGMENT_DTYPE is None:
+        SEGMENT_DTYPE = np.dtype([("in_off", "<u8"), ("out_off", "<u8"), ("nbytes", "<u8"),
+                                  ("key_slot", "<u4"), ("ctr0", "<u4"), ("nonce", "u1", (12,)),
+                                  ("reserved", "<u4")])
+        assert SEGMENT_DTYPE.itemsize == SEGMENT_BYTES
+    return SEGMENT_DTYPE
+
+
+def batched_workspace_bytes(nsegs: int) -> int:
+    return int(lib().aes_batched_workspace_bytes(nsegs))
+
+
+def _tune(tune):
+    if tune is None:
+        return None
+    if isinstance(tune, BatchTune):
+        return tune
+    return BatchTune(tune.get("layout", 0), tune.get("wg_size", 0), tune.get("grid_per_cu", 0),
+                     tune.get("tile_blocks", 0))
+
+
+def ctr_xcrypt_batched(segs: torch.Tensor, ks_table: torch.Tensor, x: torch.Tensor,
+                       out: torch.Tensor, ws: torch.Tensor, tune=None) -> torch.Tensor:
+    """aes_ctr_xcrypt_batched: segs is a uint8 CUDA tensor holding nsegs
+    aes_segment_t records, ks_table an (nkeys, 488) uint8 CUDA tensor, x / out
+    the packed input / output buffers, ws a workspace of
+    batched_workspace_bytes(nsegs) bytes (256-byte aligned)."""
+    for t, n in ((segs, "segments"), (ks_table, "key table"), (x, "input"), (out, "output"),
+                 (ws, "workspace")):
+        _dev_u8(t, n)
+    if segs.numel() % SEGMENT_BYTES or ks_table.numel() % SCHEDULE_BYTES:
+        raise ValueError("segment / key table sizes must be whole records")
+    nsegs = segs.numel() // SEGMENT_BYTES
+    nkeys = ks_table.numel() // SCHEDULE_BYTES
+    tn = _tune(tune)
+    with torch.cuda.device(x.device):
+        st = lib().aes_ctr_xcrypt_batched(_ptr(segs), nsegs, _ptr(ks_table), nkeys, _ptr(x),
+                                          _ptr(out), ctypes.byref(tn) if tn else None, _ptr(ws),
+                                          ws.numel(), _stream(x))
+    _check(st, "aes_ctr_xcrypt_batched")
+    return out
+
+
+def batched_read_status(ws: torch.Tensor) -> int:
+    """Device status word of the last batched call (0 or AES_ERR_SEGMENT)."""
+    v = ctypes.c_int32(0)
+    with torch.cuda.device(ws.device):
+        _check(lib().aes_batched_read_status(_ptr(ws), _stream(ws), ctypes.byref(v)),
+               "aes_batched_read_status")
+    return int(v.value)
+
+
+class BatchedGraph:
+    """aes_batched_graph_create / _launch / _destroy: the batched call captured
+    with fixed pointers; rewrite the tensors' contents in place between launches."""
+
+    def __init__(self, segs, ks_table, x, out, ws, tune=None):
+        for t, n in ((segs, "segments"), (ks_table, "key table"), (x, "input"),
+                     (out, "output"), (ws, "workspace")):
+            _dev_u8(t, n)
+        self._keep = (segs, ks_table, x, out, ws)
+        self.device = x.device
+        tn = _tune(tune)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(x.device):
+            st = lib().aes_batched_graph_create(
+                _ptr(segs), segs.numel() // SEGMENT_BYTES, _ptr(ks_table),
+                ks_table.numel() // SCHEDULE_BYTES, _ptr(x), _ptr(out),
+                ctypes.byref(tn) if tn else None, _ptr(ws), ws.numel(), _stream(x),
+                ctypes.byref(h))
+        _check(st, "aes_batched_graph_create")
+        self._h = h
+
+    def launch(self):
+        with torch.cuda.device(self.device):
+            _check(lib().aes_batched_graph_launch(self._h, _stream(self._keep[2])),
+                   "aes_batched_graph_launch")
+
+    def close(self):
+        if self._h:
+            _check(lib().aes_batched_graph_destroy(self._h), "aes_batched_graph_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def device_cu_count() -> int:
     return int(lib().aes_device_cu_count())

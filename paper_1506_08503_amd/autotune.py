@@ -1,0 +1,101 @@
+"""Autotuner for the batched launch: layout, tile size and workgroup shape.
+
+The persistent batched kernel has four knobs (aes_batch_tune_t): the round
+function layout (LDS tables or bitsliced), tile_blocks (16-byte blocks per tile
+a wave claims), wg_size and grid_per_cu.  ``tune_batched`` times every
+candidate on the caller's own batch with HIP events and keeps the fastest;
+results are cached in a JSON file keyed by device name and a coarse class of
+the batch (segment count and total bytes, rounded to powers of two), so a
+serving process tunes once per shape class.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import torch
+
+from . import aesmi
+
+DEFAULT_CACHE = os.environ.get("AESMI_TUNE_CACHE",
+                               os.path.join(os.path.expanduser("~"), ".cache", "aesmi",
+                                            "batched_tune.json"))
+
+
+def candidates(include_bitslice: bool = True) -> list[dict]:
+    out = []
+    for tile in (256, 512, 1024, 2048, 4096, 8192):
+        for wg in (512, 1024):
+            out.append({"layout": aesmi.LAYOUT_TTABLE, "tile_blocks": tile, "wg_size": wg,
+                        "grid_per_cu": 1})
+    out.append({"layout": aesmi.LAYOUT_TTABLE, "tile_blocks": 2048, "wg_size": 1024,
+                "grid_per_cu": 2})
+    if include_bitslice:
+        for tile in (2048, 4096):
+            for wg, gpc in ((256, 2), (128, 4)):
+                out.append({"layout": aesmi.LAYOUT_BITSLICE, "tile_blocks": tile, "wg_size": wg,
+                            "grid_per_cu": gpc})
+    return out
+
+
+def shape_class(nsegs: int, nbytes: int) -> str:
+    return "segs2^%d-bytes2^%d" % (max(0, math.ceil(math.log2(max(nsegs, 1)))),
+                                   max(0, math.ceil(math.log2(max(nbytes, 1)))))
+
+
+def time_launch(fn, reps: int = 3) -> float:
+    """Median milliseconds of fn() over reps timed runs (one warm-up)."""
+    fn()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(path, data):
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def tune_batched(dbatch, reps: int = 3, cache_path: str | None = DEFAULT_CACHE,
+                 include_bitslice: bool = True, force: bool = False):
+    """Pick the fastest tune for this DeviceBatch; returns (tune, table) where
+    table lists (tune, ms) for every candidate that was timed."""
+    dev = torch.cuda.get_device_name(dbatch.device)
+    key = "%s|%s" % (dev, shape_class(dbatch.batch.lengths.size, dbatch.nbytes))
+    cache = _load(cache_path) if cache_path else {}
+    if not force and key in cache:
+        return cache[key]["tune"], cache[key]["table"]
+    table = []
+    for cand in candidates(include_bitslice):
+        ms = time_launch(lambda: dbatch.run(cand), reps)
+        table.append((cand, ms))
+    table.sort(key=lambda r: r[1])
+    best = table[0][0]
+    if cache_path:
+        cache[key] = {"tune": best, "table": table}
+        _save(cache_path, cache)
+    return best, table

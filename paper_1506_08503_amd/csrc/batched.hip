@@ -1,10 +1,314 @@
-// batched.hip -- placeholder until the batched kernel lands.
+// batched.hip -- many messages, each with its own key, nonce and counter, in
+// one persistent launch over a device segment table.
+//
+// Sec. II lets every row (message) of the plaintext matrix carry its own IV
+// and key schedule (the per-row V and K) and vectorizes all rows at once.
+// Here rows have uneven lengths, so the unit of work is a tile: tile_blocks
+// consecutive 16-byte blocks of one message.  Two kernels run back to back on
+// the caller's stream:
+//   1. prepare (one workgroup): validates every segment, counts its tiles,
+//      writes the exclusive prefix sums tile_start[0..nsegs] and clears the
+//      tile counter and the status word in the workspace.  Invalid segments
+//      get no tiles and set the status word to AES_ERR_SEGMENT.
+//   2. persistent CTR kernel (a fixed grid of workgroups per CU): each wave
+//      claims tile t with one atomic add, finds its segment with a 64-way
+//      ballot search over tile_start (three rounds for 10^4 segments), loads
+//      that segment's key schedule and nonce, and runs the T-table or the
+//      bitsliced round function on the tile.  The LDS tables are filled once
+//      per workgroup; they do not depend on the key.
+// Neither kernel uses a memset, so the pair can be captured in a HIP graph and
+// replayed after the segment table or the data have been rewritten in place.
+#include <hip/hip_runtime.h>
+
+#include "bitslice_dev.hpp"
 #include "internal.hpp"
+#include "ttable_dev.hpp"
+
 namespace aesmi {
-size_t batched_workspace_bytes(uint32_t nsegs) { return 256 + 8 * (size_t)nsegs; }
-hipError_t batched_ctr(const aes_segment_t *, uint32_t, const aes_key_schedule_t *, uint32_t,
-                       const uint8_t *, uint8_t *, const aes_batch_tune_t *, void *, hipStream_t)
+namespace {
+
+struct WsHeader {
+    int32_t status;
+    uint32_t counter;
+    uint32_t ntiles;
+    uint32_t tile_blocks;
+};
+
+constexpr size_t kWsHeader = 256;
+
+__device__ __forceinline__ uint32_t *tile_start_of(void *ws)
 {
-    return hipErrorNotSupported;
+    return reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + kWsHeader);
 }
+
+// Tiles of one segment, or 0 when it is empty or invalid (then *bad is set).
+__device__ uint32_t segment_tiles(const aes_segment_t &sg, const aes_key_schedule_t *ks_table,
+                                  uint32_t nkeys, uint32_t tile_blocks, bool *bad)
+{
+    const uint64_t nblk = (sg.nbytes + 15u) >> 4;
+    bool ok = sg.key_slot < nkeys && sg.reserved == 0 && (sg.in_off & 15u) == 0 &&
+              (sg.out_off & 15u) == 0 && (uint64_t)sg.ctr0 + nblk <= (1ull << 32);
+    if (ok && nblk) {
+        const uint32_t nr = ks_table[sg.key_slot].nr;
+        ok = nr == 10 || nr == 12 || nr == 14;
+    }
+    if (!ok) {
+        *bad = true;
+        return 0;
+    }
+    return (uint32_t)((nblk + tile_blocks - 1) / tile_blocks);
+}
+
+__global__ __launch_bounds__(1024) void batched_prepare(const aes_segment_t *__restrict__ segs,
+                                                        uint32_t nsegs,
+                                                        const aes_key_schedule_t *__restrict__ ks_table,
+                                                        uint32_t nkeys, void *ws,
+                                                        uint32_t tile_blocks)
+{
+    __shared__ uint32_t part[1024];
+    __shared__ int bad_any;
+    WsHeader *h = static_cast<WsHeader *>(ws);
+    uint32_t *start = tile_start_of(ws);
+    const uint32_t nt = blockDim.x, tid = threadIdx.x;
+    if (tid == 0)
+        bad_any = 0;
+    // contiguous chunk of segments per thread
+    const uint32_t per = (nsegs + nt - 1) / nt;
+    const uint32_t lo = min(nsegs, tid * per), hi = min(nsegs, lo + per);
+    bool bad = false;
+    uint32_t sum = 0;
+    for (uint32_t s = lo; s < hi; ++s)
+        sum += segment_tiles(segs[s], ks_table, nkeys, tile_blocks, &bad);
+    part[tid] = sum;
+    __syncthreads();
+    if (bad)
+        bad_any = 1;
+    // inclusive scan of the per-thread sums (Hillis-Steele in LDS)
+    for (uint32_t off = 1; off < nt; off <<= 1) {
+        uint32_t v = tid >= off ? part[tid - off] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - sum;   // exclusive prefix of this chunk
+    for (uint32_t s = lo; s < hi; ++s) {
+        bool b2 = false;
+        start[s] = run;
+        run += segment_tiles(segs[s], ks_table, nkeys, tile_blocks, &b2);
+    }
+    __syncthreads();
+    if (tid == nt - 1) {
+        start[nsegs] = part[nt - 1];
+        h->ntiles = part[nt - 1];
+        h->counter = 0;
+        h->tile_blocks = tile_blocks;
+        h->status = bad_any ? (int32_t)AES_ERR_SEGMENT : (int32_t)AES_OK;
+    }
+}
+
+// Segment holding tile t: the last s with tile_start[s] <= t (empty segments
+// share their start with the next one).  Each round splits the candidate
+// range into 64 pieces, one per lane, and keeps the last piece whose first
+// entry is <= t.
+__device__ __forceinline__ uint32_t find_segment(const uint32_t *__restrict__ start,
+                                                 uint32_t nsegs, uint32_t t, uint32_t lane)
+{
+    uint32_t lo = 0, hi = nsegs;
+    while (hi - lo > 1) {
+        const uint32_t step = (hi - lo + 63u) / 64u;
+        const uint32_t idx = lo + lane * step;
+        const bool ok = idx < hi && start[idx] <= t;
+        const uint64_t m = __ballot(ok);
+        const uint32_t last = 63u - (uint32_t)__clzll((long long)m);
+        lo += last * step;
+        hi = min(lo + step, hi);
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t claim_tile(WsHeader *h, uint32_t lane)
+{
+    uint32_t t = 0;
+    if (lane == 0)
+        t = atomicAdd(&h->counter, 1u);
+    return __builtin_amdgcn_readfirstlane(t);
+}
+
+struct TileJob {
+    const u32x4 *in;
+    u32x4 *out;
+    const aes_key_schedule_t *ks;
+    uint64_t b0, b1, nfull;
+    uint32_t tail, ctr0, n0, n1, n2;
+};
+
+__device__ __forceinline__ TileJob make_job(const aes_segment_t *__restrict__ segs,
+                                            const uint32_t *__restrict__ start, uint32_t s,
+                                            uint32_t t, uint32_t tile_blocks,
+                                            const aes_key_schedule_t *__restrict__ ks_table,
+                                            const uint8_t *in_base, uint8_t *out_base)
+{
+    const aes_segment_t &sg = segs[s];
+    TileJob j;
+    const uint64_t nblk = (sg.nbytes + 15u) >> 4;
+    j.in = reinterpret_cast<const u32x4 *>(in_base + sg.in_off);
+    j.out = reinterpret_cast<u32x4 *>(out_base + sg.out_off);
+    j.ks = ks_table + sg.key_slot;
+    j.b0 = (uint64_t)(t - start[s]) * tile_blocks;
+    j.b1 = min(j.b0 + tile_blocks, nblk);
+    j.nfull = sg.nbytes >> 4;
+    j.tail = (uint32_t)(sg.nbytes & 15u);
+    j.ctr0 = sg.ctr0;
+    const uint32_t *nw = reinterpret_cast<const uint32_t *>(sg.nonce);
+    j.n0 = nw[0];
+    j.n1 = nw[1];
+    j.n2 = nw[2];
+    return j;
+}
+
+// Blocks [b0, b1) of one message on one wave with the table kernel: whole
+// 256-counter groups with the round-1/2 precomputation when the counters are
+// group aligned, four blocks per lane otherwise, then the rest one per lane.
+template <int NR>
+__device__ void ttable_tile(const TileJob &j, const char *lds, const Lc &lc, uint32_t lane)
+{
+    const uint32_t *rk = j.ks->rk_enc;
+    const uint32_t u0 = j.n0 ^ rk[0], u1 = j.n1 ^ rk[1], u2 = j.n2 ^ rk[2];
+    const uint32_t pre[4] = {xor3(TL(0, u0, 0), TL(1, u1, 1), TL(2, u2, 2)) ^ rk[4],
+                             xor3(TL(0, u1, 0), TL(1, u2, 1), TL(3, u0, 3)) ^ rk[5],
+                             xor3(TL(0, u2, 0), TL(2, u0, 2), TL(3, u1, 3)) ^ rk[6],
+                             xor3(TL(1, u0, 1), TL(2, u1, 2), TL(3, u2, 3)) ^ rk[7]};
+    const uint64_t hi = min(j.b1, j.nfull);
+    uint64_t b = j.b0;
+    if (((j.ctr0 + (uint32_t)b) & 255u) == 0 && b + 256 <= hi) {
+        uint32_t r2[4][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t s0 = pre[0] ^ TL(3, ((lane + 64u * q) << 24) ^ rk[3], 3);
+            r2[q][0] = TL(0, s0, 0);
+            r2[q][1] = TL(3, s0, 3);
+            r2[q][2] = TL(2, s0, 2);
+            r2[q][3] = TL(1, s0, 1);
+        }
+        for (; b + 256 <= hi; b += 256)
+            ctr_group<NR>(rk, j.in, j.out, b + lane, j.ctr0 + (uint32_t)b, pre, r2, lds, lc);
+    }
+    for (; b + 256 <= hi; b += 256)
+        ctr_blocks<NR, 4>(rk, j.in, j.out, b + lane, 64, j.ctr0, pre[0], pre[1], pre[2], pre[3],
+                          lds, lc);
+    for (uint64_t i = b + lane; i < hi; i += 64)
+        ctr_blocks<NR, 1>(rk, j.in, j.out, i, 0, j.ctr0, pre[0], pre[1], pre[2], pre[3], lds, lc);
+    if (j.tail && j.b1 == j.nfull + 1 && lane == 0) {
+        uint32_t s1[1][4] = {{u0, u1, u2, bswap32(j.ctr0 + (uint32_t)j.nfull) ^ rk[3]}};
+        enc_rounds<NR, 1, 1>(s1, rk, lds, lc);
+        const uint8_t *src = reinterpret_cast<const uint8_t *>(j.in + j.nfull);
+        uint8_t *dst = reinterpret_cast<uint8_t *>(j.out + j.nfull);
+        for (uint32_t k = 0; k < j.tail; ++k)
+            dst[k] = src[k] ^ (uint8_t)(s1[0][k >> 2] >> (8 * (k & 3u)));
+    }
+}
+
+__global__ __launch_bounds__(1024) void batched_ttable_kernel(
+    const aes_segment_t *__restrict__ segs, uint32_t nsegs,
+    const aes_key_schedule_t *__restrict__ ks_table, const uint8_t *in_base,
+    uint8_t *out_base, void *ws)
+{
+    __shared__ __attribute__((aligned(16))) char lds[kEncLdsBytes];
+    fill_tables(lds, false);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const Lc lc = make_lc(lane);
+    WsHeader *h = static_cast<WsHeader *>(ws);
+    const uint32_t *start = tile_start_of(ws);
+    const uint32_t ntiles = h->ntiles, tile_blocks = h->tile_blocks;
+    for (;;) {
+        const uint32_t t = claim_tile(h, lane);
+        if (t >= ntiles)
+            break;
+        const uint32_t s = find_segment(start, nsegs, t, lane);
+        const TileJob j = make_job(segs, start, s, t, tile_blocks, ks_table, in_base, out_base);
+        switch (j.ks->nr) {
+        case 10: ttable_tile<10>(j, lds, lc, lane); break;
+        case 12: ttable_tile<12>(j, lds, lc, lane); break;
+        case 14: ttable_tile<14>(j, lds, lc, lane); break;
+        default: break;
+        }
+    }
+}
+
+template <int NR>
+__device__ void bitslice_tile(const TileJob &j)
+{
+    const uint32_t *rk = j.ks->rk_enc;
+    const uint32_t w0 = j.n0 ^ rk[0], w1 = j.n1 ^ rk[1], w2 = j.n2 ^ rk[2];
+    for (uint64_t c = j.b0; c < j.b1; c += 2048)
+        bs_ctr_batch<NR>(rk, j.in, j.out, j.nfull, j.tail, w0, w1, w2, j.ctr0, c);
+}
+
+__global__ __launch_bounds__(256) void batched_bitslice_kernel(
+    const aes_segment_t *__restrict__ segs, uint32_t nsegs,
+    const aes_key_schedule_t *__restrict__ ks_table, const uint8_t *in_base,
+    uint8_t *out_base, void *ws)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    WsHeader *h = static_cast<WsHeader *>(ws);
+    const uint32_t *start = tile_start_of(ws);
+    const uint32_t ntiles = h->ntiles, tile_blocks = h->tile_blocks;
+    for (;;) {
+        const uint32_t t = claim_tile(h, lane);
+        if (t >= ntiles)
+            break;
+        const uint32_t s = find_segment(start, nsegs, t, lane);
+        const TileJob j = make_job(segs, start, s, t, tile_blocks, ks_table, in_base, out_base);
+        switch (j.ks->nr) {
+        case 10: bitslice_tile<10>(j); break;
+        case 12: bitslice_tile<12>(j); break;
+        case 14: bitslice_tile<14>(j); break;
+        default: break;
+        }
+    }
+}
+
+}  // namespace
+
+size_t batched_workspace_bytes(uint32_t nsegs)
+{
+    const size_t bytes = kWsHeader + 4u * ((size_t)nsegs + 1u);
+    return (bytes + 255u) & ~(size_t)255u;
+}
+
+hipError_t batched_ctr(const aes_segment_t *segs, uint32_t nsegs,
+                       const aes_key_schedule_t *ks_table, uint32_t nkeys,
+                       const uint8_t *in_base, uint8_t *out_base,
+                       const aes_batch_tune_t *tune, void *ws, hipStream_t stream)
+{
+    uint32_t layout = tune ? tune->layout : 0u;
+    if (layout == AES_LAYOUT_AUTO)
+        layout = AES_LAYOUT_TTABLE;
+    const bool bs = layout == AES_LAYOUT_BITSLICE;
+    uint32_t wg = tune && tune->wg_size ? tune->wg_size : (bs ? 256u : 1024u);
+    uint32_t per_cu = tune && tune->grid_per_cu ? tune->grid_per_cu : (bs ? 2u : 1u);
+    uint32_t tile = tune && tune->tile_blocks ? tune->tile_blocks : 2048u;
+    if (wg < 64 || wg % 64 || wg > (bs ? 256u : 1024u))
+        return hipErrorInvalidConfiguration;
+    if (bs && tile % 2048u)
+        return hipErrorInvalidConfiguration;
+    if (tile % 64u)
+        return hipErrorInvalidConfiguration;
+    const int cu = device_cu_count() > 0 ? device_cu_count() : 256;
+    hipLaunchKernelGGL(batched_prepare, dim3(1), dim3(1024), 0, stream, segs, nsegs, ks_table,
+                       nkeys, ws, tile);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const uint32_t grid = (uint32_t)cu * per_cu;
+    if (bs)
+        hipLaunchKernelGGL(batched_bitslice_kernel, dim3(grid), dim3(wg), 0, stream, segs, nsegs,
+                           ks_table, in_base, out_base, ws);
+    else
+        hipLaunchKernelGGL(batched_ttable_kernel, dim3(grid), dim3(wg), 0, stream, segs, nsegs,
+                           ks_table, in_base, out_base, ws);
+    return hipGetLastError();
+}
+
 }  // namespace aesmi

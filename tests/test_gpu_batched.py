@@ -1,0 +1,227 @@
+"""GPU parity of the batched persistent kernel (aes_ctr_xcrypt_batched).
+
+Every segment must equal the CPU oracle's CTR of that message alone, with its
+own key, nonce and counter (tolerance 0), for both round-function layouts and
+several tile sizes; invalid segments are reported and left untouched; graph
+replays equal eager runs; the full 10,000-message workload equals a loop of
+plain per-message launches.
+"""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1506_08503_amd as am
+from paper_1506_08503_amd import batch as bt
+from paper_1506_08503_amd import autotune
+from paper_1506_08503_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+TUNES = [None,
+         {"layout": am.LAYOUT_TTABLE, "tile_blocks": 64, "wg_size": 256, "grid_per_cu": 2},
+         {"layout": am.LAYOUT_TTABLE, "tile_blocks": 256, "wg_size": 1024, "grid_per_cu": 1},
+         {"layout": am.LAYOUT_TTABLE, "tile_blocks": 4096, "wg_size": 512, "grid_per_cu": 1},
+         {"layout": am.LAYOUT_BITSLICE, "tile_blocks": 2048, "wg_size": 256, "grid_per_cu": 2},
+         {"layout": am.LAYOUT_BITSLICE, "tile_blocks": 4096, "wg_size": 64, "grid_per_cu": 4}]
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def mixed_case(seed=77, nrandom=300):
+    """Messages of edge-case and random lengths, 128/192/256-bit keys, counters
+    aligned and unaligned to 256, some close to the 2^32 limit."""
+    g = _rng(seed)
+    edge = [0, 1, 15, 16, 17, 31, 32, 33, 16 * 255, 16 * 256, 16 * 256 + 1, 16 * 2048,
+            16 * 2049 + 7, 16 * 4096 * 3 + 5]
+    lengths = np.array(edge + wl.log_uniform_lengths(g, nrandom, 1 << 18).tolist(), np.int64)
+    n = lengths.size
+    key_bytes = g.choice([16, 24, 32], size=n)
+    keys = [g.bytes(int(k)) for k in key_bytes]
+    nonces = np.frombuffer(g.bytes(12 * n), np.uint8).reshape(n, 12)
+    ctr0 = np.where(g.random(n) < 0.5, 0, g.integers(0, 2 ** 31, size=n)).astype(np.uint64)
+    ctr0[:4] = [2 ** 32 - 1, 2 ** 32 - 1, 2 ** 32 - 1, 2 ** 32 - 2]   # 0/1/1/2 blocks
+    ctr0[5] = 2 ** 32 - 2                                            # 17 bytes: 2 blocks
+    nblk = (lengths + 15) // 16
+    assert np.all(ctr0 + nblk <= 2 ** 32)
+    in_off, total = wl.pack_offsets(lengths)
+    # outputs land in a different order with gaps, to catch offset mix-ups
+    perm = g.permutation(n)
+    out_off = np.zeros(n, np.int64)
+    pos = 0
+    for i in perm:
+        out_off[i] = pos
+        pos += (int(lengths[i]) + 15) // 16 * 16 + 16 * int(g.integers(0, 3))
+    pt = np.frombuffer(g.bytes(total), np.uint8).copy()
+    return dict(lengths=lengths, keys=keys, nonces=nonces, ctr0=ctr0.astype(np.uint32),
+                in_off=in_off, out_off=out_off, pt=pt, out_total=pos)
+
+
+def key_table(keys, device=DEV):
+    return torch.stack([am.key_schedule(k, device) for k in keys])
+
+
+def oracle_all(oracle, case):
+    def one(i):
+        a, n = int(case["in_off"][i]), int(case["lengths"][i])
+        return oracle.ctr_xcrypt(case["keys"][i], case["nonces"][i].tobytes(),
+                                 int(case["ctr0"][i]), case["pt"][a:a + n])
+    with ThreadPoolExecutor(8) as ex:
+        return list(ex.map(one, range(case["lengths"].size)))
+
+
+@pytest.fixture(scope="module")
+def mixed(oracle):
+    case = mixed_case()
+    case["expected"] = oracle_all(oracle, case)
+    return case
+
+
+def run_case(case, tune, in_place=False):
+    n = case["lengths"].size
+    segs_h = bt.segment_table(case["in_off"], case["in_off"] if in_place else case["out_off"],
+                              case["lengths"], np.arange(n, dtype=np.uint32), case["ctr0"],
+                              case["nonces"])
+    segs = torch.from_numpy(segs_h.view(np.uint8).copy()).to(DEV)
+    kt = key_table(case["keys"])
+    x = torch.from_numpy(case["pt"]).to(DEV)
+    out = x if in_place else torch.full((case["out_total"] + 16,), 0xA5, dtype=torch.uint8,
+                                        device=DEV)
+    ws = bt.workspace(n, DEV)
+    am.ctr_xcrypt_batched(segs, kt, x, out, ws, tune)
+    assert am.batched_read_status(ws) == 0
+    return out.cpu().numpy(), ws
+
+
+@pytest.mark.parametrize("tune", TUNES, ids=lambda t: "default" if t is None else
+                         "%s-t%d-w%d-g%d" % ("bs" if t["layout"] == 2 else "tt", t["tile_blocks"],
+                                             t["wg_size"], t["grid_per_cu"]))
+def test_batched_mixed_matches_oracle(mixed, tune):
+    out, _ = run_case(mixed, tune)
+    off = mixed["out_off"]
+    for i, exp in enumerate(mixed["expected"]):
+        got = out[int(off[i]):int(off[i]) + exp.size]
+        assert np.array_equal(got, exp), (i, int(mixed["lengths"][i]), int(mixed["ctr0"][i]))
+    # bytes outside every segment stay untouched
+    mask = np.ones(out.size, bool)
+    for i, exp in enumerate(mixed["expected"]):
+        mask[int(off[i]):int(off[i]) + exp.size] = False
+    assert np.all(out[mask] == 0xA5)
+
+
+def test_batched_in_place(mixed):
+    out, _ = run_case(mixed, None, in_place=True)
+    for i, exp in enumerate(mixed["expected"]):
+        a = int(mixed["in_off"][i])
+        assert np.array_equal(out[a:a + exp.size], exp), i
+
+
+def test_batched_invalid_segments(oracle):
+    g = _rng(9)
+    n = 8
+    lengths = np.full(n, 16 * 300 + 3, np.int64)
+    in_off, total = wl.pack_offsets(lengths)
+    keys = [g.bytes(16) for _ in range(4)]
+    nonces = np.frombuffer(g.bytes(12 * n), np.uint8).reshape(n, 12)
+    slots = np.array([0, 1, 4, 2, 3, 0, 1, 2], np.uint32)       # slot 4 does not exist
+    ctr0 = np.zeros(n, np.uint32)
+    ctr0[6] = 2 ** 32 - 10                                       # counter overflow
+    segs_h = bt.segment_table(in_off, in_off, lengths, slots, ctr0, nonces)
+    segs_h["in_off"][4] += 8                                     # misaligned
+    segs_h["reserved"][5] = 1                                    # reserved must be 0
+    pt = np.frombuffer(g.bytes(total + 16), np.uint8).copy()
+    x = torch.from_numpy(pt).to(DEV)
+    out = torch.full_like(x, 0x5A)
+    ws = bt.workspace(n, DEV)
+    am.ctr_xcrypt_batched(torch.from_numpy(segs_h.view(np.uint8).copy()).to(DEV),
+                          key_table(keys), x, out, ws)
+    assert am.batched_read_status(ws) == -7          # AES_ERR_SEGMENT
+    o = out.cpu().numpy()
+    for i in range(n):
+        a, ln = int(in_off[i]), int(lengths[i])
+        if i in (2, 4, 5, 6):
+            assert np.all(o[a:a + ln] == 0x5A), i
+        else:
+            exp = oracle.ctr_xcrypt(keys[slots[i]], nonces[i].tobytes(), 0, pt[a:a + ln])
+            assert np.array_equal(o[a:a + ln], exp), i
+
+
+def test_batched_graph_replays(mixed):
+    """A captured graph replayed three times, the input rewritten in place with
+    eager work and synchronizations in between; every replay equals an eager
+    batched run on the same data."""
+    n = mixed["lengths"].size
+    segs_h = bt.segment_table(mixed["in_off"], mixed["out_off"], mixed["lengths"],
+                              np.arange(n, dtype=np.uint32), mixed["ctr0"], mixed["nonces"])
+    segs = torch.from_numpy(segs_h.view(np.uint8).copy()).to(DEV)
+    kt = key_table(mixed["keys"])
+    x = torch.from_numpy(mixed["pt"]).to(DEV)
+    out = torch.zeros(mixed["out_total"] + 16, dtype=torch.uint8, device=DEV)
+    ws = bt.workspace(n, DEV)
+    graph = am.BatchedGraph(segs, kt, x, out, ws)
+    ref_out = torch.zeros_like(out)
+    ws2 = bt.workspace(n, DEV)
+    try:
+        for rep in range(3):
+            x.add_(rep + 1)                       # new data in the same buffer (eager)
+            torch.cuda.synchronize()
+            graph.launch()
+            torch.cuda.synchronize()
+            am.ctr_xcrypt_batched(segs, kt, x, ref_out, ws2)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref_out), rep
+            assert am.batched_read_status(ws) == 0
+    finally:
+        graph.close()
+
+
+def test_autotune_small():
+    """The tuner times every candidate on the caller's batch and its pick gives
+    the same bytes as the default launch and as one plain launch per message."""
+    db = bt.DeviceBatch(wl.batched_inputs(nmsg=300, max_len=1 << 18, seed=5), DEV)
+    best, table = autotune.tune_batched(db, reps=1, cache_path=None)
+    assert table and best == table[0][0]
+    ref = db.run(None).clone()
+    assert torch.equal(db.run(best), ref)
+    db.out.zero_()
+    assert torch.equal(db.run_plain_loop(), ref)
+
+
+@pytest.mark.slow
+def test_batched_full_workload(oracle):
+    """10,000 messages, log-uniform 1 B .. 1 MiB, own AES-128 keys and nonces:
+    one persistent launch equals 10,000 plain launches byte for byte, and the
+    oracle agrees on every message up to 64 KiB and on sampled blocks of the
+    larger ones."""
+    b = wl.batched_inputs()
+    db = bt.DeviceBatch(b, DEV)
+    got = db.run().clone()
+    assert db.status() == 0
+    db.out.zero_()
+    loop = db.run_plain_loop().clone()
+    assert torch.equal(got, loop)
+    pt = db.x.cpu().numpy()
+    out = got.cpu().numpy()
+    g = _rng(11)
+    small = [i for i in range(b.lengths.size) if b.lengths[i] <= 1 << 16]
+
+    def check_small(i):
+        a, n = int(b.offsets[i]), int(b.lengths[i])
+        exp = oracle.ctr_xcrypt(b.keys[i].tobytes(), b.nonces[i].tobytes(), 0, pt[a:a + n])
+        return np.array_equal(out[a:a + n], exp)
+    with ThreadPoolExecutor(8) as ex:
+        assert all(ex.map(check_small, small))
+    for i in range(b.lengths.size):
+        if b.lengths[i] <= 1 << 16:
+            continue
+        a, n = int(b.offsets[i]), int(b.lengths[i])
+        nb = (n + 15) // 16
+        idx = np.unique(np.concatenate([[0, nb - 1], g.integers(0, nb, 16)])).astype(np.uint64)
+        ks = oracle.ctr_keystream_at(b.keys[i].tobytes(), b.nonces[i].tobytes(), 0, idx)
+        for j, blk in enumerate(idx.tolist()):
+            lo, hi = a + 16 * blk, min(a + 16 * blk + 16, a + n)
+            assert np.array_equal(out[lo:hi], pt[lo:hi] ^ ks[j][:hi - lo]), (i, blk)
