@@ -1,0 +1,469 @@
+"""Continuous-batching request loop for AES-CTR encryption requests.
+
+Requests arrive over time (open-loop arrival schedule), each with its own key
+(from a key set), nonce, first counter and payload.  The loop
+
+* admits requests in arrival order while the device bytes they hold (input
+  plus output) fit an HBM budget; a request larger than the whole budget is
+  rejected;
+* keeps expanded key schedules in a fixed-size device cache (LRU; a schedule
+  used by an in-flight batch is pinned and never evicted); misses are expanded
+  on the device (aes_expand_keys_device) right before the batch that needs
+  them;
+* closes a batch when a launch slot is free and either nothing is running,
+  the queued bytes reach a size threshold or the oldest queued request has
+  waited longer than a time window; each batch is one aes_ctr_xcrypt_batched
+  launch over a segment table on one of several streams, so batches overlap
+  on the device and requests keep being admitted while others run;
+* retires batches as their events complete, releasing budget and key pins,
+  and records per-request latency = completion - scheduled arrival.
+
+The many-rows-at-once framing is the paper's (sec. II-III: many short
+messages, each with its own IV and key); the scheduling is this library's.
+
+The executor (what runs a batch) is pluggable: ``GpuExecutor`` launches the
+HIP kernels; the tests drive the same loop with a CPU executor that computes
+results with the oracle, to check admission, caching and accounting without a
+GPU.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+# ----------------------------------------------------------------- requests
+@dataclass
+class Requests:
+    """Struct-of-arrays request set, sorted by arrival time."""
+    arrival: np.ndarray      # seconds from the start, non-decreasing
+    key_id: np.ndarray       # index into the key set
+    nonce: np.ndarray        # n x 12 uint8
+    ctr0: np.ndarray         # uint32
+    size: np.ndarray         # bytes
+    in_off: np.ndarray       # byte offset of the payload in the input pool (16-aligned)
+
+    def __len__(self):
+        return int(self.size.size)
+
+
+def requests_from_stream(rs, pool_bytes: int, seed: int = 1) -> Requests:
+    """Place the payloads of a workloads.RequestStream in an input pool of
+    pool_bytes bytes (random 16-aligned offsets; payloads may share bytes)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    size = np.minimum(rs.sizes, pool_bytes).astype(np.int64)
+    room = (pool_bytes - size) // 16
+    in_off = (g.integers(0, np.iinfo(np.int64).max, size=size.size) % (room + 1)) * 16
+    return Requests(arrival=np.asarray(rs.arrival_s, np.float64),
+                    key_id=np.asarray(rs.key_slot, np.int64), nonce=rs.nonces,
+                    ctr0=np.zeros(size.size, np.uint32), size=size, in_off=in_off)
+
+
+# ---------------------------------------------------------------- key cache
+class KeyCache:
+    """Which keys of the key set have their schedule in which cache slot.
+
+    Bookkeeping only (host side); the executor owns the device table.  A slot
+    is pinned once per in-flight batch that uses it."""
+
+    def __init__(self, nslots: int, nkeys: int):
+        self.nslots = nslots
+        self.slot_of = np.full(nkeys, -1, np.int64)
+        self.key_of = np.full(nslots, -1, np.int64)
+        self.last_use = np.zeros(nslots, np.int64)
+        self.pins = np.zeros(nslots, np.int64)
+        self.tick = 0
+        self.hits = 0
+        self.misses = 0
+
+    def acquire(self, key_ids: np.ndarray):
+        """Slots for a batch's keys.  Returns (slot per request, distinct slots,
+        [(slot, key_id) to fill]) or None when too few slots are unpinned."""
+        uniq = np.unique(key_ids)
+        have = self.slot_of[uniq] >= 0
+        missing = uniq[~have]
+        if missing.size:
+            candidates = np.nonzero(self.pins == 0)[0]
+            # keep slots this batch already hits
+            keep = np.zeros(self.nslots, bool)
+            keep[self.slot_of[uniq[have]]] = True
+            candidates = candidates[~keep[candidates]]
+            if candidates.size < missing.size:
+                return None
+            # empty slots first, then least recently used
+            order = np.lexsort((self.last_use[candidates], self.key_of[candidates] >= 0))
+            victims = candidates[order[:missing.size]]
+            old = self.key_of[victims]
+            self.slot_of[old[old >= 0]] = -1
+            self.key_of[victims] = missing
+            self.slot_of[missing] = victims
+        self.tick += 1
+        slots = self.slot_of[uniq]
+        self.last_use[slots] = self.tick
+        self.pins[slots] += 1
+        per_req = self.slot_of[key_ids]
+        nmiss_req = int(np.isin(key_ids, missing).sum())
+        self.misses += nmiss_req
+        self.hits += int(key_ids.size) - nmiss_req
+        fills = list(zip(self.slot_of[missing].tolist(), missing.tolist()))
+        return per_req, slots, fills
+
+    def max_prefix(self, key_ids: np.ndarray) -> int:
+        """Largest k such that acquire(key_ids[:k]) can succeed: the missing
+        keys of the prefix must fit into the unpinned slots that do not hold a
+        key the prefix hits."""
+        if key_ids.size == 0:
+            return 0
+        _, first = np.unique(key_ids, return_index=True)
+        new = np.zeros(key_ids.size, np.int64)
+        new[first] = 1
+        slot = self.slot_of[key_ids]
+        miss = new * (slot < 0)
+        hit_free = new * ((slot >= 0) & (self.pins[np.maximum(slot, 0)] == 0))
+        need = np.cumsum(miss + hit_free)
+        return int(np.searchsorted(need, int((self.pins == 0).sum()), "right"))
+
+    def release(self, slots: np.ndarray):
+        self.pins[slots] -= 1
+        assert np.all(self.pins >= 0)
+
+
+# -------------------------------------------------------------------- batches
+@dataclass
+class Batch:
+    first: int                  # request index range [first, last)
+    last: int
+    nbytes: int                 # payload bytes
+    held: int                   # budget bytes held (input + output)
+    slots: np.ndarray           # distinct key slots pinned
+    handle: object = None
+    out_off: np.ndarray = None  # output offset of each request in the batch buffer
+
+
+class ServedResults:
+    """Outputs of a run, materialized on demand (request i -> a view into the
+    output buffer of the batch that served it; None when rejected)."""
+
+    def __init__(self, executor, n):
+        self.ex = executor
+        self.batch_of = np.full(n, -1, np.int64)
+        self.index_in = np.zeros(n, np.int64)
+        self.handles = []
+
+    def add(self, handle, first, last):
+        self.batch_of[first:last] = len(self.handles)
+        self.index_in[first:last] = np.arange(last - first)
+        self.handles.append(handle)
+
+    def __len__(self):
+        return self.batch_of.size
+
+    def __getitem__(self, i):
+        b = int(self.batch_of[i])
+        if b < 0:
+            return None
+        return self.ex.output(self.handles[b], int(self.index_in[i]))
+
+
+@dataclass
+class Stats:
+    completed: int = 0
+    rejected: int = 0
+    bytes: int = 0
+    batches: int = 0
+    elapsed_s: float = 0.0
+    latency_s: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    admission_wait_s: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    key_hits: int = 0
+    key_misses: int = 0
+    max_inflight: int = 0
+    max_held: int = 0
+
+    def summary(self) -> dict:
+        lat = self.latency_s[np.isfinite(self.latency_s)]
+        q = (lambda p: float(np.percentile(lat, p)) * 1e3) if lat.size else (lambda p: None)
+        return {"requests": self.completed, "rejected": self.rejected,
+                "GBps": self.bytes / self.elapsed_s / 1e9 if self.elapsed_s else None,
+                "req_per_s": self.completed / self.elapsed_s if self.elapsed_s else None,
+                "p50_ms": q(50), "p99_ms": q(99), "max_ms": q(100),
+                "mean_batch": self.completed / max(self.batches, 1), "batches": self.batches,
+                "key_hit_rate": self.key_hits / max(self.key_hits + self.key_misses, 1),
+                "max_inflight": self.max_inflight, "max_held_bytes": self.max_held}
+
+
+class Server:
+    """The request loop (see the module docstring)."""
+
+    def __init__(self, executor, key_cache: KeyCache, hbm_budget: int,
+                 max_batch_bytes: int = 64 << 20, max_batch_reqs: int = 8192,
+                 window_s: float = 50e-6, clock=time.perf_counter):
+        self.ex = executor
+        self.kc = key_cache
+        self.budget = hbm_budget
+        self.max_batch_bytes = max_batch_bytes
+        self.max_batch_reqs = max_batch_reqs
+        self.window_s = window_s
+        self.clock = clock
+
+    @staticmethod
+    def footprint(size: np.ndarray) -> np.ndarray:
+        """Device bytes a request holds while in flight: its input and its
+        16-byte padded output."""
+        return size + (size + 15) // 16 * 16
+
+    def run(self, reqs: Requests, realtime: bool = True) -> tuple[Stats, ServedResults]:
+        n = len(reqs)
+        fp = self.footprint(reqs.size)
+        complete = np.full(n, np.nan)
+        admitted = np.full(n, np.nan)
+        results = ServedResults(self.ex, n)
+        st = Stats()
+        held = 0
+        inflight: deque[Batch] = deque()
+        qh = 0          # first request not yet admitted
+        t0 = self.clock()
+        while qh < n or inflight:
+            now = self.clock() - t0
+            arrived = n if not realtime else int(np.searchsorted(reqs.arrival, now, "right"))
+            # retire finished batches (in completion order per slot)
+            progressed = False
+            for b in list(inflight):
+                if self.ex.done(b.handle):
+                    inflight.remove(b)
+                    tdone = self.clock() - t0
+                    complete[b.first:b.last] = tdone
+                    results.add(b.handle, b.first, b.last)
+                    held -= b.held
+                    self.kc.release(b.slots)
+                    self.ex.release(b.handle)
+                    st.completed += b.last - b.first
+                    st.bytes += b.nbytes
+                    progressed = True
+            # reject what can never fit
+            while qh < arrived and fp[qh] > self.budget:
+                st.rejected += 1
+                complete[qh] = np.inf
+                qh += 1
+                progressed = True
+            if qh < arrived and self.ex.free_slots() > 0:
+                queued_bytes = int(reqs.size[qh:arrived].sum())
+                oldest_wait = now - reqs.arrival[qh] if realtime else 0.0
+                if (not inflight or queued_bytes >= self.max_batch_bytes
+                        or oldest_wait >= self.window_s or arrived == n):
+                    b = self._form_batch(reqs, fp, qh, arrived, held)
+                    if b is not None:
+                        admitted[b.first:b.last] = self.clock() - t0
+                        b.handle = self.ex.submit(reqs, b.first, b.last, b.per_req_slots,
+                                                  b.fills)
+                        held += b.held
+                        inflight.append(b)
+                        st.batches += 1
+                        st.max_inflight = max(st.max_inflight, len(inflight))
+                        st.max_held = max(st.max_held, held)
+                        qh = b.last
+                        progressed = True
+            if not progressed:
+                self.ex.idle()
+        st.elapsed_s = self.clock() - t0
+        ok = np.isfinite(complete)
+        st.latency_s = np.where(ok, complete - reqs.arrival, np.inf)
+        st.admission_wait_s = np.where(ok, admitted - reqs.arrival, np.inf)
+        st.key_hits, st.key_misses = self.kc.hits, self.kc.misses
+        return st, results
+
+    def _form_batch(self, reqs, fp, qh, arrived, held):
+        """Largest FIFO prefix of the queue within the budget and batch limits."""
+        room = self.budget - held
+        cum_fp = np.cumsum(fp[qh:arrived])
+        cum_b = np.cumsum(reqs.size[qh:arrived])
+        k = int(np.searchsorted(cum_fp, room, "right"))
+        k = min(k, int(np.searchsorted(cum_b, self.max_batch_bytes, "right")) or 1,
+                self.max_batch_reqs, arrived - qh)
+        if k > 0:
+            k = min(k, self.kc.max_prefix(reqs.key_id[qh:qh + k]))
+        if k == 0:
+            return None
+        got = self.kc.acquire(reqs.key_id[qh:qh + k])
+        assert got is not None
+        per_req, slots, fills = got
+        b = Batch(first=qh, last=qh + k, nbytes=int(cum_b[k - 1]), held=int(cum_fp[k - 1]),
+                  slots=slots)
+        b.per_req_slots = per_req
+        b.fills = fills
+        return b
+
+
+# ------------------------------------------------------------------ executors
+class GpuExecutor:
+    """Runs batches with aes_ctr_xcrypt_batched on `nstreams` streams.
+
+    Per stream it owns a workspace, pinned host staging for the segment table
+    and for missing keys, and their device copies, so a batch costs two small
+    host-to-device copies, at most three key-expansion launches (one per key
+    length), one scatter into the key table and the two batched kernels."""
+
+    def __init__(self, pool, keys: list, nslots: int, nstreams: int = 2,
+                 max_segs: int = 8192, tune=None):
+        import torch
+        from . import aesmi
+        from .batch import workspace
+        self.torch, self.am = torch, aesmi
+        self.pool = pool
+        self.dev = pool.device
+        self.keys = keys
+        self.key_len = np.array([len(k) for k in keys], np.int64)
+        key_pad = np.zeros((len(keys), 32), np.uint8)
+        for i, k in enumerate(keys):
+            key_pad[i, :len(k)] = np.frombuffer(k, np.uint8)
+        self.key_pad = key_pad
+        self.table = torch.zeros((nslots, aesmi.SCHEDULE_BYTES), dtype=torch.uint8,
+                                 device=self.dev)
+        self.tune = tune
+        self.max_segs = max_segs
+        sb = aesmi.SEGMENT_BYTES
+        self.slots = []
+        for _ in range(nstreams):
+            self.slots.append({
+                "stream": torch.cuda.Stream(self.dev),
+                "ws": workspace(max_segs, self.dev),
+                "segs_h": torch.empty(max_segs * sb, dtype=torch.uint8, pin_memory=True),
+                "segs_d": torch.empty(max_segs * sb, dtype=torch.uint8, device=self.dev),
+                "keys_h": torch.empty(max_segs * 40, dtype=torch.uint8, pin_memory=True),
+                "keys_d": torch.empty(max_segs * 40, dtype=torch.uint8, device=self.dev),
+                "busy": False})
+        # key slot -> (stream slot, event) of an in-flight batch that filled it
+        self.filled_by = {}
+
+    def free_slots(self):
+        return sum(not s["busy"] for s in self.slots)
+
+    def _fill_keys(self, slot, fills):
+        """Expand the missing keys into their cache slots on this stream."""
+        torch, am = self.torch, self.am
+        n = len(fills)
+        sl = np.array([f[0] for f in fills], np.int64)
+        kid = np.array([f[1] for f in fills], np.int64)
+        order = np.argsort(self.key_len[kid], kind="stable")
+        sl, kid = sl[order], kid[order]
+        # staging: n x 32 key bytes, then n int64 slot indices
+        raw = slot["keys_h"][:n * 40].numpy()
+        raw[:n * 32] = self.key_pad[kid].reshape(-1)
+        raw[n * 32:n * 40] = sl.astype("<i8").view(np.uint8)
+        dev = slot["keys_d"][:n * 40]
+        dev.copy_(slot["keys_h"][:n * 40], non_blocking=True)
+        kbytes = dev[:n * 32].view(n, 32)
+        idx = dev[n * 32:n * 40].view(torch.int64)
+        lens = self.key_len[kid]
+        for kb in (16, 24, 32):
+            lo, hi = np.searchsorted(lens, kb), np.searchsorted(lens, kb, "right")
+            if hi > lo:
+                exp = am.expand_keys_device(kbytes[lo:hi, :kb].contiguous())
+                self.table.index_copy_(0, idx[lo:hi], exp)
+
+    def submit(self, reqs, first, last, key_slots, fills):
+        torch, am = self.torch, self.am
+        from .batch import segment_table
+        slot = next(s for s in self.slots if not s["busy"])
+        n = last - first
+        if n > self.max_segs:
+            raise ValueError("batch larger than max_segs")
+        slot["busy"] = True
+        size = reqs.size[first:last]
+        pad = (size + 15) // 16 * 16
+        out_off = np.zeros(n, np.int64)
+        np.cumsum(pad[:-1], out=out_off[1:])
+        total = int(pad.sum())
+        segs = segment_table(reqs.in_off[first:last], out_off, size, key_slots.astype(np.uint32),
+                             reqs.ctr0[first:last], reqs.nonce[first:last])
+        s = slot["stream"]
+        with torch.cuda.stream(s):
+            # schedules another stream's in-flight batch is still writing
+            if self.filled_by:
+                for ks in np.unique(key_slots).tolist():
+                    fb = self.filled_by.get(ks)
+                    if fb is not None and fb[0] is not slot:
+                        s.wait_event(fb[1])
+            if fills:
+                self._fill_keys(slot, fills)
+                kev = torch.cuda.Event()
+                kev.record(s)
+                for sl, _ in fills:
+                    self.filled_by[sl] = (slot, kev)
+            hb = slot["segs_h"][:n * am.SEGMENT_BYTES]
+            hb.numpy()[:] = segs.view(np.uint8)
+            db = slot["segs_d"][:n * am.SEGMENT_BYTES]
+            db.copy_(hb, non_blocking=True)
+            out = torch.empty(max(total, 16), dtype=torch.uint8, device=self.dev)
+            am.ctr_xcrypt_batched(db, self.table, self.pool, out, slot["ws"], self.tune)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return {"slot": slot, "event": ev, "out": out, "out_off": out_off, "size": size,
+                "fills": [f[0] for f in fills]}
+
+    def done(self, h):
+        return h["event"].query()
+
+    def output(self, h, j):
+        o = int(h["out_off"][j])
+        return h["out"][o:o + int(h["size"][j])]
+
+    def release(self, h):
+        h["slot"]["busy"] = False
+        for sl in h["fills"]:
+            fb = self.filled_by.get(sl)
+            if fb is not None and fb[0] is h["slot"]:
+                del self.filled_by[sl]
+
+    def idle(self):
+        pass
+
+
+class OracleExecutor:
+    """CPU executor for tests: results from the CPU oracle, completion after a
+    modelled device time (launch latency + bytes / rate) on the server clock."""
+
+    def __init__(self, oracle, pool: np.ndarray, keys: list, nslots: int, clock,
+                 nstreams: int = 2, latency_s: float = 20e-6, rate_Bps: float = 1e9):
+        self.o, self.pool, self.keys = oracle, pool, keys
+        self.clock = clock
+        self.latency, self.rate = latency_s, rate_Bps
+        self.nstreams = nstreams
+        self.busy = 0
+        self.resident = {}      # key slot -> key id whose schedule is "on the device"
+        self.fill_log = []
+        self.next_free = 0.0
+
+    def free_slots(self):
+        return self.nstreams - self.busy
+
+    def submit(self, reqs, first, last, key_slots, fills):
+        self.busy += 1
+        for sl, kid in fills:
+            self.resident[sl] = kid
+            self.fill_log.append((sl, kid))
+        outs = []
+        for j, i in enumerate(range(first, last)):
+            kid = self.resident[int(key_slots[j])]
+            assert kid == reqs.key_id[i], "key cache handed out a stale slot"
+            a, n = int(reqs.in_off[i]), int(reqs.size[i])
+            outs.append(self.o.ctr_xcrypt(self.keys[kid], reqs.nonce[i].tobytes(),
+                                          int(reqs.ctr0[i]), self.pool[a:a + n]))
+        start = max(self.clock(), self.next_free)
+        t_done = start + self.latency + int(reqs.size[first:last].sum()) / self.rate
+        self.next_free = t_done
+        return {"t": t_done, "outs": outs}
+
+    def done(self, h):
+        return self.clock() >= h["t"]
+
+    def output(self, h, j):
+        return h["outs"][j]
+
+    def release(self, h):
+        self.busy -= 1
+
+    def idle(self):
+        pass
