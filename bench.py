@@ -39,10 +39,16 @@ def parse():
     p.add_argument("--nbytes", type=int, default=4 << 30)
     p.add_argument("--layout", choices=["auto", "ttable", "bitslice"], default="auto")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--op", choices=["ctr", "ecb-enc", "ecb-dec"], default="ctr",
+                   help="operation of the stream leg (the headline metric is ctr)")
+    p.add_argument("--key-bytes", type=int, default=16, choices=[16, 24, 32])
     p.add_argument("--mode", choices=["aes", "copy"], default="aes",
                    help="copy: time a plain device copy of the same buffer instead "
                         "(reference for HBM counter calibration)")
     p.add_argument("--cpu-threads", type=int, default=0)
+    p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--no-serving", action="store_true")
+    p.add_argument("--serving-requests", type=int, default=100_000)
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     return p.parse_args()
 
@@ -61,6 +67,75 @@ def cpu_baseline(inp, threads):
             "kind": "oracle",
             "sample": "first %d MiB of the 4 GiB AES-128-CTR plaintext, %d host threads, "
                       "%.2f s" % (sample >> 20, threads, dt)}
+
+
+def batched_leg():
+    """10,000 messages (log-uniform 1 B .. 1 MiB, own AES-128 key and nonce):
+    one persistent launch (autotuned, replayed as a HIP graph) against a loop
+    of one plain aes_ctr_xcrypt launch per message."""
+    import torch
+    from paper_1506_08503_amd import autotune, batch, workloads as wl
+    b = wl.batched_inputs()
+    db = batch.DeviceBatch(b)
+    tune, table = autotune.tune_batched(db, reps=3, cache_path=None)
+    g = db.graph(tune)
+    ms = autotune.time_launch(g.launch, 10)
+    ms_default = autotune.time_launch(lambda: db.run(None), 5)
+    torch.cuda.synchronize()
+    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record()
+    db.run_plain_loop()
+    e.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    loop_ms = a.elapsed_time(e)
+    g.close()
+    return {"workload": "10000 messages, log-uniform 1 B..1 MiB, own AES-128 key+nonce",
+            "bytes": db.nbytes, "GBps_batched": round(db.nbytes / ms / 1e6, 1),
+            "ms_batched_graph": round(ms, 4), "ms_batched_default_tune": round(ms_default, 4),
+            "GBps_plain_loop": round(db.nbytes / loop_ms / 1e6, 2),
+            "ms_plain_loop": round(loop_ms, 3), "ms_plain_loop_wall": round(wall, 3),
+            "speedup": round(loop_ms / ms, 1), "tune": tune}
+
+
+def serving_leg(nreq):
+    """Open-loop Poisson arrivals of AES-128/256 CTR requests (lognormal sizes,
+    median 4 KiB, sigma 2, clipped to 16 MiB; 1,024 keys; 4 GiB HBM budget),
+    payloads already in device memory.  Capacity is measured closed-loop, then
+    latency at 50% and 80% of it; key caches of 1,024 and 256 slots."""
+    import numpy as np
+    import torch
+    from paper_1506_08503_amd import serve, workloads as wl
+    pool_bytes = 256 << 20
+    g = np.random.Generator(np.random.PCG64(wl.SEED_SERVING + 1))
+    pool = torch.from_numpy(np.frombuffer(g.bytes(pool_bytes), np.uint8).copy()).cuda()
+
+    def run(rate, n, nslots, closed=False):
+        rs = wl.serving_inputs(n, rate, nkeys=1024)
+        reqs = serve.requests_from_stream(rs, pool_bytes)
+        if closed:
+            reqs.arrival[:] = 0.0
+        ex = serve.GpuExecutor(pool, rs.keys, nslots, nstreams=2, max_segs=8192)
+        srv = serve.Server(ex, serve.KeyCache(nslots, len(rs.keys)), hbm_budget=4 << 30,
+                           max_batch_reqs=8192, window_s=50e-6)
+        st, _ = srv.run(reqs)
+        torch.cuda.synchronize()
+        s = st.summary()
+        return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
+
+    run(1e5, 5000, 1024, closed=True)            # warm-up
+    out = {"workload": "%d requests, lognormal sizes median 4 KiB sigma 2 (<=16 MiB), "
+                       "1024 keys (half AES-128, half AES-256), 4 GiB budget" % nreq}
+    for nslots in (1024, 256):
+        cap = run(1e5, nreq, nslots, closed=True)
+        rate = cap["req_per_s"]
+        res = {"capacity": cap}
+        for rho in (0.5, 0.8):
+            res["rho%.1f" % rho] = dict(run(rho * rate, nreq, nslots), offered_req_per_s=
+                                        round(rho * rate))
+        out["key_slots_%d" % nslots] = res
+    return out
 
 
 def load_traffic(path, kernel):
@@ -84,7 +159,7 @@ def main():
 
     layout = {"auto": am.LAYOUT_AUTO, "ttable": am.LAYOUT_TTABLE,
               "bitslice": am.LAYOUT_BITSLICE}[args.layout]
-    inp = wl.stream_inputs(wl.SEED_STREAM, args.nbytes)
+    inp = wl.stream_inputs(wl.SEED_STREAM, args.nbytes, key_bytes=args.key_bytes)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     x = torch.empty(inp.nbytes, dtype=torch.uint8, device=dev)
@@ -97,6 +172,10 @@ def main():
     def step():
         if args.mode == "copy":
             y.copy_(x)
+        elif args.op == "ecb-enc":
+            am.ecb_encrypt(ks, x, out=y, **kw)
+        elif args.op == "ecb-dec":
+            am.ecb_decrypt(ks, x, out=y, **kw)
         else:
             am.ctr_xcrypt(ks, inp.nonce, inp.ctr0, x, out=y, **kw)
 
@@ -122,16 +201,26 @@ def main():
     value = inp.nbytes / (ms_per_step * 1e-3) / 1e9
     alg_bytes = 32 * nblocks
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-    kernel_name = "ctr_ttable_kernel" if args.layout != "bitslice" else "ctr_bitslice_kernel"
-    traffic = load_traffic(args.traffic_json, kernel_name)
+    kernel_name = {("ctr", False): "ctr_grouped_kernel", ("ctr", True): "ctr_bitslice_kernel",
+                   ("ecb-enc", False): "ecb_ttable_kernel<false, 4>",
+                   ("ecb-enc", True): "ecb_bitslice_kernel<false>",
+                   ("ecb-dec", False): "ecb_ttable_kernel<true, 4>",
+                   ("ecb-dec", True): "ecb_bitslice_kernel<true>"}[(args.op,
+                                                                    args.layout == "bitslice")]
+    # counters were taken for the default workload only (AES-128 CTR, 4 GiB)
+    default_cfg = (args.op, args.key_bytes, args.nbytes, args.layout) == ("ctr", 16, 4 << 30,
+                                                                           "auto")
+    traffic = load_traffic(args.traffic_json, kernel_name) if default_cfg else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": kernel_name,
                 "kernel_ms_avg": round(avg_ms, 4), "kernel_ms_min": round(min(kernel_ms), 4)}
     if args.layout != "bitslice":
-        # On-chip limits of the table kernel: 148 LDS reads per AES-128 block
-        # (4 in round 1, 16 in each of rounds 2..10) against 32 reads/clk/CU.
-        lds_reads = 148 * nblocks
+        # On-chip limit of the table kernels: LDS reads per block -- CTR:
+        # 16 (Nr - 2) (rounds 1-2 come from per-thread and per-256-counter
+        # group precomputation); ECB: 16 Nr -- against 32 reads/clk/CU.
+        nr = {16: 10, 24: 12, 32: 14}[args.key_bytes]
+        lds_reads = (16 * (nr - 2) if args.op == "ctr" else 16 * nr) * nblocks
         roofline["lds_treads_per_s"] = round(lds_reads / (avg_ms * 1e-3) / 1e12, 3)
         roofline["lds_frac_at_2p4ghz"] = round(lds_reads / (avg_ms * 1e-3) / 1e12
                                                / LDS_PEAK_TREADS, 4)
@@ -140,14 +229,26 @@ def main():
                           "GBps_read_plus_write": round(2 * inp.nbytes / (avg_ms * 1e-3) / 1e9,
                                                         1)}), flush=True)
         return
-    out = {"metric": "AES-128-CTR GB/s at 4 GiB", "value": round(value, 2), "unit": "GB/s",
+    metric = "AES-128-CTR GB/s at 4 GiB"
+    if args.op != "ctr" or args.key_bytes != 16 or args.nbytes != 4 << 30:
+        metric = "AES-%d-%s GB/s at %d MiB" % (8 * args.key_bytes, args.op.upper(),
+                                               args.nbytes >> 20)
+    out = {"metric": metric, "value": round(value, 2), "unit": "GB/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "u8",
            "data": "synthetic (PCG64 seed 0xAE502 uniform bytes)",
-           "config": {"workload": "aes128-ctr-4GiB", "nbytes": inp.nbytes,
+           "config": {"workload": "aes%d-%s-%dMiB" % (8 * args.key_bytes, args.op,
+                                                         args.nbytes >> 20),
+                      "nbytes": inp.nbytes,
                       "blocks": nblocks, "layout": args.layout, "in_place": False},
            "roofline": roofline}
+    del x, y
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = batched_leg()
+    if not args.no_serving:
+        out["serving"] = serving_leg(args.serving_requests)
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(inp, threads)
