@@ -49,6 +49,9 @@ def parse():
     p.add_argument("--no-batched", action="store_true")
     p.add_argument("--no-serving", action="store_true")
     p.add_argument("--serving-requests", type=int, default=100_000)
+    p.add_argument("--sweep", action="store_true",
+                   help="instead of the benchmark: the paper's Fig. 3 workloads (rate vs "
+                        "number of 16-byte messages; rate vs length for 128 messages)")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     return p.parse_args()
 
@@ -138,6 +141,40 @@ def serving_leg(nreq):
     return out
 
 
+def sweep_fig3():
+    """Rates of the paper's Fig. 3 workloads (sec. IV): AES-128 CBC encryption
+    and decryption of N 16-byte messages for growing N, and of 128 messages of
+    growing length; CTR of the same bytes beside them.  One JSON line."""
+    import numpy as np
+    import torch
+    import paper_1506_08503_amd as am
+    from paper_1506_08503_amd import autotune
+    g = np.random.Generator(np.random.PCG64(0xF163))
+    ks = am.key_schedule(g.bytes(16))
+    rows = []
+
+    def measure(nmsg, msg_bytes):
+        n = nmsg * msg_bytes
+        x = torch.from_numpy(np.frombuffer(g.bytes(n), np.uint8).copy()).cuda()
+        iv = torch.from_numpy(np.frombuffer(g.bytes(16 * nmsg), np.uint8).copy()).cuda()
+        y = torch.empty_like(x)
+        z = torch.empty_like(x)
+        reps = 20 if n < (64 << 20) else 5
+        t_enc = autotune.time_launch(lambda: am.cbc_encrypt(ks, iv, x, nmsg, out=y), reps)
+        t_dec = autotune.time_launch(lambda: am.cbc_decrypt(ks, iv, y, nmsg, out=z), reps)
+        t_ctr = autotune.time_launch(lambda: am.ctr_xcrypt(ks, b"\0" * 12, 0, x, out=z), reps)
+        assert torch.equal(am.cbc_decrypt(ks, iv, y, nmsg), x)
+        return {"messages": nmsg, "msg_bytes": msg_bytes, "total_bytes": n,
+                "cbc_enc_GBps": round(n / t_enc / 1e6, 3), "cbc_dec_GBps": round(n / t_dec / 1e6, 3),
+                "ctr_GBps": round(n / t_ctr / 1e6, 3), "cbc_enc_ms": round(t_enc, 4)}
+
+    for e in range(4, 27, 2):                      # 16 .. 2^26 sixteen-byte messages
+        rows.append(dict(measure(1 << e, 16), curve="16-byte messages"))
+    for e in range(4, 21, 2):                      # 128 messages of 16 B .. 1 MiB
+        rows.append(dict(measure(128, 1 << e), curve="128 messages"))
+    return {"sweep": "paper Fig. 3 workloads, AES-128", "rows": rows}
+
+
 def load_traffic(path, kernel):
     try:
         with open(path) as f:
@@ -157,6 +194,9 @@ def main():
     import paper_1506_08503_amd as am
     from paper_1506_08503_amd import workloads as wl
 
+    if args.sweep:
+        print(json.dumps(sweep_fig3()), flush=True)
+        return
     layout = {"auto": am.LAYOUT_AUTO, "ttable": am.LAYOUT_TTABLE,
               "bitslice": am.LAYOUT_BITSLICE}[args.layout]
     inp = wl.stream_inputs(wl.SEED_STREAM, args.nbytes, key_bytes=args.key_bytes)

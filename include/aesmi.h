@@ -133,6 +133,29 @@ aes_status_t aes_ctr_xcrypt_ex(const aes_key_schedule_t *ks_dev, const uint8_t *
                                void *stream);
 
 /*
+ * aes_cbc_encrypt / aes_cbc_decrypt -- CBC over a matrix of messages, the
+ * mode of the paper's listings (App. A1 encryption, App. A4 decryption):
+ * nmsg rows of msg_bytes bytes each, row-major and contiguous in in_dev /
+ * out_dev.  Block i of row r is enciphered after XOR with ciphertext block
+ * i-1 of the same row (the row's IV for i = 0); decryption XORs the
+ * previous ciphertext block after the inverse cipher.  The paper zero-pads
+ * rows to a whole number of blocks (App. A1); here the caller passes padded
+ * rows: msg_bytes % 16 != 0 is AES_ERR_LENGTH.
+ *   iv_dev     device; iv_stride 16: one 16-byte IV per row (the per-row V of
+ *              sec. II), iv_stride 0: one IV shared by all rows (App. A1)
+ * Encryption is parallel across rows only (serial along a row) and may run
+ * in place; decryption is parallel across all blocks and must not run in
+ * place (AES_ERR_OVERLAP if the ranges intersect).  nmsg == 0 or
+ * msg_bytes == 0 is a no-op.
+ */
+aes_status_t aes_cbc_encrypt(const aes_key_schedule_t *ks_dev, const void *iv_dev,
+                             size_t iv_stride, const void *in_dev, void *out_dev,
+                             size_t nmsg, size_t msg_bytes, void *stream);
+aes_status_t aes_cbc_decrypt(const aes_key_schedule_t *ks_dev, const void *iv_dev,
+                             size_t iv_stride, const void *in_dev, void *out_dev,
+                             size_t nmsg, size_t msg_bytes, void *stream);
+
+/*
  * Batched CTR: many messages, each with its own key schedule, nonce and
  * counter, in one persistent launch (the per-row V and K of sec. II applied to
  * messages of uneven length).  Message s reads nbytes bytes at

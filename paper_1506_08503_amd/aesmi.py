@@ -95,6 +95,8 @@ def lib():
             "aes_ecb_decrypt_ex": ([vp, vp, vp, sz, ctypes.POINTER(Launch), vp], st),
             "aes_ctr_xcrypt": ([vp, vp, u32, vp, vp, sz, vp], st),
             "aes_ctr_xcrypt_ex": ([vp, vp, u32, vp, vp, sz, ctypes.POINTER(Launch), vp], st),
+            "aes_cbc_encrypt": ([vp, vp, sz, vp, vp, sz, sz, vp], st),
+            "aes_cbc_decrypt": ([vp, vp, sz, vp, vp, sz, sz, vp], st),
             "aes_batched_workspace_bytes": ([u32], sz),
             "aes_ctr_xcrypt_batched": ([vp, u32, vp, u32, vp, vp, ctypes.POINTER(BatchTune),
                                         vp, sz, vp], st),
@@ -239,6 +241,40 @@ def ctr_xcrypt(ks: torch.Tensor, nonce: bytes, ctr0: int, x: torch.Tensor,
                                      ctypes.byref(lc), _stream(x))
     _check(st, "aes_ctr_xcrypt")
     return out
+
+
+# ---------------------------------------------------------------------- CBC
+def _cbc(fname, ks, iv, x, nmsg, out):
+    _dev_u8(x, "input")
+    _dev_u8(iv, "iv")
+    if x.numel() % max(nmsg, 1):
+        raise ValueError("input must hold nmsg rows of equal length")
+    msg_bytes = x.numel() // nmsg if nmsg else 0
+    if iv.numel() == 16:
+        stride = 0
+    elif iv.numel() == 16 * nmsg:
+        stride = 16
+    else:
+        raise ValueError("iv must be 16 bytes or 16 bytes per row")
+    out = _out_like(x, out)
+    with torch.cuda.device(x.device):
+        st = getattr(lib(), fname)(_ks_arg(ks), _ptr(iv), stride, _ptr(x), _ptr(out), nmsg,
+                                   msg_bytes, _stream(x))
+    _check(st, fname)
+    return out
+
+
+def cbc_encrypt(ks: torch.Tensor, iv: torch.Tensor, x: torch.Tensor, nmsg: int = 1,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """aes_cbc_encrypt: x holds nmsg rows of equal, 16-byte multiple length;
+    iv is one 16-byte IV or one per row."""
+    return _cbc("aes_cbc_encrypt", ks, iv, x, nmsg, out)
+
+
+def cbc_decrypt(ks: torch.Tensor, iv: torch.Tensor, x: torch.Tensor, nmsg: int = 1,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """aes_cbc_decrypt (out of place)."""
+    return _cbc("aes_cbc_decrypt", ks, iv, x, nmsg, out)
 
 
 # ------------------------------------------------------------------- batched

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <stdint.h>
 #include <new>
 #include <string.h>
 
@@ -193,6 +194,43 @@ aes_status_t aes_ctr_xcrypt(const aes_key_schedule_t *ks_dev, const uint8_t *non
                             void *stream)
 {
     return aes_ctr_xcrypt_ex(ks_dev, nonce, ctr0, in_dev, out_dev, nbytes, nullptr, stream);
+}
+
+static aes_status_t cbc_common(bool decrypt, const aes_key_schedule_t *ks, const void *iv,
+                               size_t iv_stride, const void *in, void *out, size_t nmsg,
+                               size_t msg_bytes, void *stream)
+{
+    if (nmsg == 0 || msg_bytes == 0)
+        return AES_OK;
+    if (!ks || !iv || !in || !out)
+        return AES_ERR_NULL;
+    if (msg_bytes % 16)
+        return AES_ERR_LENGTH;
+    if (iv_stride != 0 && iv_stride != 16)
+        return AES_ERR_CONFIG;
+    if (!aligned16(in) || !aligned16(out) || !aligned16(iv))
+        return AES_ERR_ALIGN;
+    if (nmsg > SIZE_MAX / msg_bytes)
+        return AES_ERR_LENGTH;
+    const size_t nbytes = nmsg * msg_bytes;
+    if (decrypt ? (in == out || bad_overlap(in, out, nbytes)) : bad_overlap(in, out, nbytes))
+        return AES_ERR_OVERLAP;
+    return from_hip(cbc(decrypt, ks, iv, iv_stride ? 1u : 0u, in, out, nmsg, msg_bytes / 16,
+                        static_cast<hipStream_t>(stream)));
+}
+
+aes_status_t aes_cbc_encrypt(const aes_key_schedule_t *ks_dev, const void *iv_dev,
+                             size_t iv_stride, const void *in_dev, void *out_dev, size_t nmsg,
+                             size_t msg_bytes, void *stream)
+{
+    return cbc_common(false, ks_dev, iv_dev, iv_stride, in_dev, out_dev, nmsg, msg_bytes, stream);
+}
+
+aes_status_t aes_cbc_decrypt(const aes_key_schedule_t *ks_dev, const void *iv_dev,
+                             size_t iv_stride, const void *in_dev, void *out_dev, size_t nmsg,
+                             size_t msg_bytes, void *stream)
+{
+    return cbc_common(true, ks_dev, iv_dev, iv_stride, in_dev, out_dev, nmsg, msg_bytes, stream);
 }
 
 size_t aes_batched_workspace_bytes(uint32_t nsegs)

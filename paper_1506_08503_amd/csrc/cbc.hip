@@ -1,0 +1,182 @@
+// cbc.hip -- CBC over a matrix of messages, the mode the paper implements.
+//
+// App. A1 / A4 encrypt N messages of M bytes (the rows of an N x M matrix)
+// at once: block i of a row is enciphered after adding the previous
+// ciphertext block of the same row (the row's IV for block 0), and deciphering
+// adds the previous ciphertext block after the inverse cipher.
+//   * Encryption is serial along a row and parallel across rows: one lane
+//     per row, two rows per lane interleaved for instruction-level
+//     parallelism, the chaining value kept in registers.
+//   * Decryption has no serial dependence (every ciphertext block is known):
+//     one lane per block, like ECB, plus one extra 16-byte load of the
+//     previous ciphertext block (or the IV).
+// The round functions are the T-table ones of ttable_dev.hpp.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "ttable_dev.hpp"
+
+namespace aesmi {
+namespace {
+
+constexpr int kRowsPerLane = 2;
+
+template <int NR, int MPL>
+__device__ void cbc_enc_body(const uint32_t *__restrict__ rk, const u32x4 *__restrict__ in,
+                             u32x4 *__restrict__ out, const u32x4 *__restrict__ iv,
+                             uint32_t iv_step, uint64_t nmsg, uint64_t nblk, const char *lds,
+                             const Lc &lc)
+{
+    const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t m0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m0 < nmsg;
+         m0 += nthreads * MPL) {
+        uint32_t chain[MPL][4];
+        bool valid[MPL];
+        uint64_t row[MPL];
+#pragma unroll
+        for (int j = 0; j < MPL; ++j) {
+            row[j] = m0 + j * nthreads;
+            valid[j] = row[j] < nmsg;
+            const u32x4 v = valid[j] ? iv[row[j] * iv_step] : u32x4{0, 0, 0, 0};
+            chain[j][0] = v.x;
+            chain[j][1] = v.y;
+            chain[j][2] = v.z;
+            chain[j][3] = v.w;
+        }
+        // the next plaintext block is loaded one step ahead, so its memory
+        // latency overlaps the rounds of the current block
+        u32x4 next[MPL];
+#pragma unroll
+        for (int j = 0; j < MPL; ++j)
+            next[j] = valid[j] ? in[row[j] * nblk] : u32x4{0, 0, 0, 0};
+        for (uint64_t b = 0; b < nblk; ++b) {
+            uint32_t s[MPL][4];
+#pragma unroll
+            for (int j = 0; j < MPL; ++j) {
+                const u32x4 x = next[j];
+                if (b + 1 < nblk)
+                    next[j] = valid[j] ? in[row[j] * nblk + b + 1] : u32x4{0, 0, 0, 0};
+                s[j][0] = x.x ^ chain[j][0] ^ rk[0];
+                s[j][1] = x.y ^ chain[j][1] ^ rk[1];
+                s[j][2] = x.z ^ chain[j][2] ^ rk[2];
+                s[j][3] = x.w ^ chain[j][3] ^ rk[3];
+            }
+            enc_rounds<NR, 1, MPL>(s, rk, lds, lc);
+#pragma unroll
+            for (int j = 0; j < MPL; ++j) {
+                chain[j][0] = s[j][0];
+                chain[j][1] = s[j][1];
+                chain[j][2] = s[j][2];
+                chain[j][3] = s[j][3];
+                if (valid[j])
+                    out[row[j] * nblk + b] = u32x4{s[j][0], s[j][1], s[j][2], s[j][3]};
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void cbc_enc_kernel(const aes_key_schedule_t *__restrict__ ks,
+                                                       const u32x4 *__restrict__ in,
+                                                       u32x4 *__restrict__ out,
+                                                       const u32x4 *__restrict__ iv,
+                                                       uint32_t iv_step, uint64_t nmsg,
+                                                       uint64_t nblk)
+{
+    __shared__ __attribute__((aligned(16))) char lds[kEncLdsBytes];
+    fill_tables(lds, false);
+    __syncthreads();
+    const Lc lc = make_lc(threadIdx.x & 63u);
+    const uint32_t *rk = ks->rk_enc;
+    switch (ks->nr) {
+    case 10: cbc_enc_body<10, kRowsPerLane>(rk, in, out, iv, iv_step, nmsg, nblk, lds, lc); break;
+    case 12: cbc_enc_body<12, kRowsPerLane>(rk, in, out, iv, iv_step, nmsg, nblk, lds, lc); break;
+    case 14: cbc_enc_body<14, kRowsPerLane>(rk, in, out, iv, iv_step, nmsg, nblk, lds, lc); break;
+    default: break;
+    }
+}
+
+// Block g = row * nblk + b.  Each thread walks g = g0 + k * T; the row and the
+// position in the row are advanced incrementally (one division per thread).
+template <int NR>
+__device__ void cbc_dec_body(const uint32_t *__restrict__ dk, const u32x4 *__restrict__ in,
+                             u32x4 *__restrict__ out, const u32x4 *__restrict__ iv,
+                             uint32_t iv_step, uint64_t nmsg, uint64_t nblk, const char *lds,
+                             const Lc &lc, uint32_t lcs)
+{
+    const uint64_t total = nmsg * nblk;
+    const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total)
+        return;
+    uint64_t row = g / nblk, pos = g - row * nblk;
+    const uint64_t drow = step / nblk, dpos = step - drow * nblk;
+    for (; g < total; g += step) {
+        const u32x4 c = in[g];
+        const u32x4 prev = pos ? in[g - 1] : iv[row * iv_step];
+        uint32_t s[1][4] = {{c.x ^ dk[0], c.y ^ dk[1], c.z ^ dk[2], c.w ^ dk[3]}};
+        dec_rounds<NR, 1>(s, dk, lds, lc, lcs);
+        out[g] = u32x4{s[0][0] ^ prev.x, s[0][1] ^ prev.y, s[0][2] ^ prev.z, s[0][3] ^ prev.w};
+        row += drow;
+        pos += dpos;
+        if (pos >= nblk) {
+            pos -= nblk;
+            row += 1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void cbc_dec_kernel(const aes_key_schedule_t *__restrict__ ks,
+                                                       const u32x4 *__restrict__ in,
+                                                       u32x4 *__restrict__ out,
+                                                       const u32x4 *__restrict__ iv,
+                                                       uint32_t iv_step, uint64_t nmsg,
+                                                       uint64_t nblk)
+{
+    __shared__ __attribute__((aligned(16))) char lds[kDecLdsBytes];
+    fill_tables(lds, true);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const Lc lc = make_lc(lane);
+    const uint32_t lcs = kSiBase | ((lane & 31u) << 2);
+    const uint32_t *dk = ks->rk_dec;
+    switch (ks->nr) {
+    case 10: cbc_dec_body<10>(dk, in, out, iv, iv_step, nmsg, nblk, lds, lc, lcs); break;
+    case 12: cbc_dec_body<12>(dk, in, out, iv, iv_step, nmsg, nblk, lds, lc, lcs); break;
+    case 14: cbc_dec_body<14>(dk, in, out, iv, iv_step, nmsg, nblk, lds, lc, lcs); break;
+    default: break;
+    }
+}
+
+}  // namespace
+
+hipError_t cbc(bool decrypt, const aes_key_schedule_t *ks, const void *iv, uint32_t iv_step,
+               const void *in, void *out, uint64_t nmsg, uint64_t nblk, hipStream_t stream)
+{
+    const int cu = device_cu_count() > 0 ? device_cu_count() : 256;
+    const u32x4 *src = static_cast<const u32x4 *>(in);
+    u32x4 *dst = static_cast<u32x4 *>(out);
+    const u32x4 *ivp = static_cast<const u32x4 *>(iv);
+    if (decrypt) {
+        const uint64_t total = nmsg * nblk;
+        uint32_t wg = 1024;
+        while (wg > 256 && (total + wg - 1) / wg < (uint64_t)cu)
+            wg >>= 1;
+        const uint64_t need = (total + wg - 1) / wg;
+        const uint32_t grid = (uint32_t)(need < (uint64_t)cu ? need : (uint64_t)cu);
+        hipLaunchKernelGGL(cbc_dec_kernel, dim3(grid), dim3(wg), 0, stream, ks, src, dst, ivp,
+                           iv_step, nmsg, nblk);
+    } else {
+        // one lane per row (two rows per lane): spread rows over the CUs first
+        uint32_t wg = 1024;
+        const uint64_t lanes = (nmsg + kRowsPerLane - 1) / kRowsPerLane;
+        while (wg > 64 && (lanes + wg - 1) / wg < (uint64_t)cu)
+            wg >>= 1;
+        const uint64_t need = (lanes + wg - 1) / wg;
+        const uint32_t grid = (uint32_t)(need < (uint64_t)cu ? need : (uint64_t)cu);
+        hipLaunchKernelGGL(cbc_enc_kernel, dim3(grid), dim3(wg), 0, stream, ks, src, dst, ivp,
+                           iv_step, nmsg, nblk);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace aesmi

@@ -35,6 +35,10 @@ hipError_t bitslice_ctr(const aes_key_schedule_t *ks, const uint32_t nonce_words
                         uint32_t ctr0, const void *in, void *out, uint64_t nbytes,
                         const aes_launch_t *launch, hipStream_t stream);
 
+// --- CBC over a matrix of messages (cbc.hip) --------------------------------
+hipError_t cbc(bool decrypt, const aes_key_schedule_t *ks, const void *iv, uint32_t iv_step,
+               const void *in, void *out, uint64_t nmsg, uint64_t nblk, hipStream_t stream);
+
 // --- device key expansion (keyexp.hip) -------------------------------------
 hipError_t expand_keys_device(const uint8_t *keys, uint32_t key_bytes, uint64_t nkeys,
                               aes_key_schedule_t *ks, hipStream_t stream);

@@ -110,6 +110,20 @@ def test_ctr_validation():
     assert L.aes_status_string(12345) == b"unknown status"
 
 
+def test_cbc_validation():
+    ks, iv, a, b = VP(0x10000), VP(0x30000), VP(0x20000), VP(0x40000)
+    for f in (L.aes_cbc_encrypt, L.aes_cbc_decrypt):
+        assert f(None, None, 16, None, None, 0, 32, None) == 0
+        assert f(None, None, 16, None, None, 5, 0, None) == 0
+        assert f(None, iv, 16, a, b, 4, 32, None) == -1
+        assert f(ks, None, 16, a, b, 4, 32, None) == -1
+        assert f(ks, iv, 16, a, b, 4, 24, None) == -3
+        assert f(ks, iv, 8, a, b, 4, 32, None) == -9
+        assert f(ks, VP(0x30008), 16, a, b, 4, 32, None) == -4
+        assert f(ks, iv, 0, a, VP(0x20010), 4, 32, None) == -5
+    assert L.aes_cbc_decrypt(ks, iv, 16, a, a, 4, 32, None) == -5   # no in-place decrypt
+
+
 def test_batched_validation():
     segs, kt, a, b, ws = VP(0x10000), VP(0x20000), VP(0x40000), VP(0x80000), VP(0x100000)
     f = L.aes_ctr_xcrypt_batched
