@@ -522,3 +522,108 @@ int oracle_cbc_decrypt(const uint8_t *key, int key_bytes, const uint8_t iv[16],
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ GCM
+ * Galois/Counter Mode, which the paper names as future work (sec. V: it
+ * needs a 128-bit Galois field).  Written from NIST SP 800-38D:
+ *   H = E(0^128); for a 96-bit IV, J0 = IV || 0^31 || 1;
+ *   C = CTR from inc32(J0)  (nonce IV, first counter 2, as oracle_ctr_xcrypt);
+ *   S = GHASH_H(A || 0-pad || C || 0-pad || [len(A)]_64 || [len(C)]_64)
+ *       with lengths in bits, big-endian;
+ *   T = E(J0) xor S.
+ * GHASH_H(X_1..X_m): Y_0 = 0, Y_i = (Y_{i-1} xor X_i) * H in GF(2^128).
+ * Field element bit order: bit 0 is the most significant bit of byte 0 and is
+ * the coefficient of x^0; the field polynomial is x^128 + x^7 + x^2 + x + 1.
+ */
+/* Product in GF(2^128) (SP 800-38D sec. 6.3, Algorithm 1): for every bit i of
+ * X (in the order above) add V when it is set, then V <- V * x, i.e. a shift
+ * towards higher coefficients (one bit right in byte order) with the
+ * reduction R = 11100001 || 0^120 when x^127 falls out. */
+void oracle_gf128_mul(const uint8_t X[16], const uint8_t Y[16], uint8_t out[16])
+{
+    uint8_t Z[16] = {0}, V[16];
+    memcpy(V, Y, 16);
+    for (int i = 0; i < 128; ++i) {
+        int xi = (X[i / 8] >> (7 - i % 8)) & 1;
+        if (xi)
+            for (int k = 0; k < 16; ++k)
+                Z[k] ^= V[k];
+        int lsb = V[15] & 1;
+        for (int k = 15; k > 0; --k)
+            V[k] = (uint8_t)((V[k] >> 1) | (V[k - 1] << 7));
+        V[0] >>= 1;
+        if (lsb)
+            V[0] ^= 0xE1;
+    }
+    memcpy(out, Z, 16);
+}
+
+/* GHASH over m whole blocks (SP 800-38D Algorithm 2). */
+void oracle_ghash(const uint8_t H[16], const uint8_t *X, size_t nblocks, uint8_t Y[16])
+{
+    uint8_t acc[16] = {0};
+    for (size_t i = 0; i < nblocks; ++i) {
+        for (int k = 0; k < 16; ++k)
+            acc[k] ^= X[16 * i + k];
+        oracle_gf128_mul(acc, H, acc);
+    }
+    memcpy(Y, acc, 16);
+}
+
+/* One GHASH step over a byte string zero-padded to whole blocks. */
+static void ghash_update(const uint8_t H[16], uint8_t acc[16], const uint8_t *p, size_t n)
+{
+    for (size_t off = 0; off < n; off += 16) {
+        size_t len = n - off < 16 ? n - off : 16;
+        for (size_t k = 0; k < len; ++k)
+            acc[k] ^= p[off + k];
+        oracle_gf128_mul(acc, H, acc);
+    }
+}
+
+/* Tag of (A, C) under key / 96-bit IV; shared by encryption and decryption. */
+static int gcm_tag(const uint8_t *key, int key_bytes, const uint8_t iv[12],
+                   const uint8_t *aad, size_t aad_len, const uint8_t *ct, size_t ct_len,
+                   uint8_t tag[16])
+{
+    uint8_t zero[16] = {0}, H[16], J0[16], EJ0[16], acc[16] = {0}, lens[16];
+    if (oracle_encrypt_block(key, key_bytes, zero, H))
+        return -1;
+    memcpy(J0, iv, 12);
+    J0[12] = J0[13] = J0[14] = 0;
+    J0[15] = 1;
+    oracle_encrypt_block(key, key_bytes, J0, EJ0);
+    ghash_update(H, acc, aad, aad_len);
+    ghash_update(H, acc, ct, ct_len);
+    uint64_t abits = (uint64_t)aad_len * 8, cbits = (uint64_t)ct_len * 8;
+    for (int k = 0; k < 8; ++k) {
+        lens[k] = (uint8_t)(abits >> (56 - 8 * k));
+        lens[8 + k] = (uint8_t)(cbits >> (56 - 8 * k));
+    }
+    ghash_update(H, acc, lens, 16);
+    for (int k = 0; k < 16; ++k)
+        tag[k] = EJ0[k] ^ acc[k];
+    return 0;
+}
+
+int oracle_gcm_encrypt(const uint8_t *key, int key_bytes, const uint8_t iv[12],
+                       const uint8_t *aad, size_t aad_len, const uint8_t *in, uint8_t *out,
+                       size_t nbytes, uint8_t tag[16])
+{
+    int rc = oracle_ctr_xcrypt(key, key_bytes, iv, 2, in, out, nbytes);
+    if (rc)
+        return rc;
+    return gcm_tag(key, key_bytes, iv, aad, aad_len, out, nbytes, tag);
+}
+
+/* Decryption returns the plaintext and the tag computed over the received
+ * ciphertext; the caller compares it with the received tag. */
+int oracle_gcm_decrypt(const uint8_t *key, int key_bytes, const uint8_t iv[12],
+                       const uint8_t *aad, size_t aad_len, const uint8_t *in, uint8_t *out,
+                       size_t nbytes, uint8_t tag[16])
+{
+    int rc = gcm_tag(key, key_bytes, iv, aad, aad_len, in, nbytes, tag);
+    if (rc)
+        return rc;
+    return oracle_ctr_xcrypt(key, key_bytes, iv, 2, in, out, nbytes);
+}

@@ -80,6 +80,12 @@ def _bind(lib):
         f = getattr(lib, name)
         f.argtypes = [u8p, c.c_int, u8p, u8p, u8p, c.c_size_t]
         f.restype = c.c_int
+    lib.oracle_gf128_mul.argtypes = [u8p, u8p, u8p]
+    lib.oracle_ghash.argtypes = [u8p, u8p, c.c_size_t, u8p]
+    for name in ("oracle_gcm_encrypt", "oracle_gcm_decrypt"):
+        f = getattr(lib, name)
+        f.argtypes = [u8p, c.c_int, u8p, u8p, c.c_size_t, u8p, u8p, c.c_size_t, u8p]
+        f.restype = c.c_int
     return lib
 
 
@@ -259,6 +265,42 @@ class Oracle:
 
     def cbc_decrypt(self, key, iv, data):
         return self._cbc(self.lib.oracle_cbc_decrypt, key, iv, data)
+
+    # -- GCM (SP 800-38D) -------------------------------------------------------
+    def gf128_mul(self, x, y):
+        x, xp = _u8(np.frombuffer(bytes(x), np.uint8))
+        y, yp = _u8(np.frombuffer(bytes(y), np.uint8))
+        out, op = _u8(np.zeros(16, np.uint8))
+        self.lib.oracle_gf128_mul(xp, yp, op)
+        return out
+
+    def ghash(self, h, blocks):
+        h, hp = _u8(np.frombuffer(bytes(h), np.uint8))
+        blocks, bp = _u8(blocks)
+        assert blocks.size % 16 == 0
+        out, op = _u8(np.zeros(16, np.uint8))
+        self.lib.oracle_ghash(hp, bp, blocks.size // 16, op)
+        return out
+
+    def _gcm(self, fn, key, iv, aad, data):
+        key, kp = _u8(np.frombuffer(bytes(key), np.uint8))
+        iv, ivp = _u8(np.frombuffer(bytes(iv), np.uint8))
+        assert iv.size == 12
+        aad, ap = _u8(np.frombuffer(bytes(aad), np.uint8) if not isinstance(aad, np.ndarray)
+                      else aad)
+        data, dp = _u8(data)
+        out, op = _u8(np.zeros_like(data))
+        tag, tp = _u8(np.zeros(16, np.uint8))
+        _check(fn(kp, key.size, ivp, ap, aad.size, dp, op, data.size, tp))
+        return out, tag
+
+    def gcm_encrypt(self, key, iv, aad, data):
+        """(ciphertext, tag)"""
+        return self._gcm(self.lib.oracle_gcm_encrypt, key, iv, aad, data)
+
+    def gcm_decrypt(self, key, iv, aad, data):
+        """(plaintext, tag computed over the received ciphertext)"""
+        return self._gcm(self.lib.oracle_gcm_decrypt, key, iv, aad, data)
 
 
 _default = None

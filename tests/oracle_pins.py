@@ -298,6 +298,99 @@ def pin_modes(o):
         raise AssertionError("counter overflow accepted")
 
 
+# -------------------------------------------------------------------- GCM
+def gf128_reference(x: bytes, y: bytes) -> bytes:
+    """GF(2^128) product written as integer polynomial arithmetic -- a
+    different method from the oracle's shift-and-add (SP 800-38D Algorithm
+    1): map each block to a polynomial (bit 0 = MSB of byte 0 = x^0),
+    carry-less multiply, reduce by x^128 + x^7 + x^2 + x + 1, map back."""
+    def to_poly(b):
+        v = int.from_bytes(b, "big")
+        return int(format(v, "0128b")[::-1], 2)
+
+    def from_poly(p):
+        return int(format(p, "0128b")[::-1], 2).to_bytes(16, "big")
+    a, b = to_poly(x), to_poly(y)
+    prod = 0
+    while b:
+        if b & 1:
+            prod ^= a
+        a <<= 1
+        b >>= 1
+    poly = (1 << 128) | 0x87
+    for deg in range(prod.bit_length() - 1, 127, -1):
+        if (prod >> deg) & 1:
+            prod ^= poly << (deg - 128)
+    return from_poly(prod)
+
+
+def pin_gf128(o):
+    """The oracle's GF(2^128) product equals the integer-polynomial product on
+    random and structured operands; x^0 (0x80 00..) is the identity; the
+    product commutes and distributes; H^(2^128) = H (Frobenius)."""
+    g = _rng(128)
+    one = bytes([0x80]) + bytes(15)
+    cases = [(g.bytes(16), g.bytes(16)) for _ in range(40)]
+    cases += [(bytes(15) + b"\x01", bytes(15) + b"\x01"), (b"\xff" * 16, b"\xff" * 16),
+              (one, g.bytes(16))]
+    for x, y in cases:
+        assert o.gf128_mul(x, y).tobytes() == gf128_reference(x, y)
+        assert o.gf128_mul(y, x).tobytes() == o.gf128_mul(x, y).tobytes()
+    for _ in range(10):
+        x, y, z = g.bytes(16), g.bytes(16), g.bytes(16)
+        yz = bytes(a ^ b for a, b in zip(y, z))
+        lhs = o.gf128_mul(x, yz)
+        rhs = o.gf128_mul(x, y) ^ o.gf128_mul(x, z)
+        assert np.array_equal(lhs, rhs)
+        assert o.gf128_mul(one, x).tobytes() == x
+    h = g.bytes(16)
+    p = h
+    for _ in range(128):
+        p = o.gf128_mul(p, p).tobytes()
+    assert p == h
+
+
+def pin_ghash(o):
+    """GHASH by Horner equals the sum of X_i * H^(m-i+1) built from the
+    reference product, and is linear in the data."""
+    g = _rng(129)
+    h = g.bytes(16)
+    blocks = np.frombuffer(g.bytes(16 * 7), np.uint8)
+    acc = bytes(16)
+    hp = h
+    for i in range(6, -1, -1):
+        term = gf128_reference(blocks[16 * i:16 * i + 16].tobytes(), hp)
+        acc = bytes(a ^ b for a, b in zip(acc, term))
+        hp = gf128_reference(hp, h)
+    assert o.ghash(h, blocks).tobytes() == acc
+    other = np.frombuffer(g.bytes(16 * 7), np.uint8)
+    assert np.array_equal(o.ghash(h, blocks ^ other), o.ghash(h, blocks) ^ o.ghash(h, other))
+
+
+def pin_gcm_vectors(o):
+    """GCM specification test cases 1-4, 13, 14; decryption reproduces the
+    plaintext and the same tag."""
+    n = 0
+    for f in _lines("gcm_vectors.txt"):
+        key, iv = bytes.fromhex(f[1]), bytes.fromhex(f[2])
+        aad = b"" if f[3] == "-" else bytes.fromhex(f[3])
+        pt = np.frombuffer(b"" if f[4] == "-" else bytes.fromhex(f[4]), np.uint8)
+        ct_exp = b"" if f[5] == "-" else bytes.fromhex(f[5])
+        ct, tag = o.gcm_encrypt(key, iv, aad, pt)
+        assert ct.tobytes() == ct_exp and tag.tobytes() == bytes.fromhex(f[6])
+        back, tag2 = o.gcm_decrypt(key, iv, aad, ct)
+        assert np.array_equal(back, pt) and np.array_equal(tag, tag2)
+        n += 1
+    assert n == 6
+    # GCM's encryption is CTR from counter 2 (J0 = IV || 1 is kept for the tag)
+    g = _rng(130)
+    key, iv = g.bytes(16), g.bytes(12)
+    msg = np.frombuffer(g.bytes(16 * 5 + 3), np.uint8)
+    ct, tag = o.gcm_encrypt(key, iv, b"", msg)
+    assert np.array_equal(ct, o.ctr_xcrypt(key, iv, 2, msg))
+
+
 ALL_PINS = [pin_paper_gf_examples, pin_gf_field, pin_rcon, pin_sbox, pin_inv_sbox,
             pin_shift_rows_paper, pin_mix_columns, pin_standard_vectors,
-            pin_paper_vectorized, pin_openssl, pin_modes]
+            pin_paper_vectorized, pin_openssl, pin_modes, pin_gf128, pin_ghash,
+            pin_gcm_vectors]

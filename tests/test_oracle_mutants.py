@@ -74,6 +74,14 @@ MUTANTS = [
      "    blk[13] = (uint8_t)(ctr >> 8);\n    blk[12] = (uint8_t)ctr;"),
     ("counter_wraps_silently", "if ((uint64_t)ctr0 + nblocks > (1ull << 32))\n        return -3;",
      "if (0)\n        return -3;"),
+    # GCM
+    ("gcm_reduction_constant", "V[0] ^= 0xE1;", "V[0] ^= 0xE0;"),
+    ("gcm_bit_order", "int xi = (X[i / 8] >> (7 - i % 8)) & 1;", "int xi = (X[i / 8] >> (i % 8)) & 1;"),
+    ("gcm_lengths_in_bytes", "uint64_t abits = (uint64_t)aad_len * 8, cbits = (uint64_t)ct_len * 8;",
+     "uint64_t abits = (uint64_t)aad_len, cbits = (uint64_t)ct_len;"),
+    ("gcm_counter_starts_at_1", "int rc = oracle_ctr_xcrypt(key, key_bytes, iv, 2, in, out, nbytes);\n    if (rc)\n        return rc;\n    return gcm_tag",
+     "int rc = oracle_ctr_xcrypt(key, key_bytes, iv, 1, in, out, nbytes);\n    if (rc)\n        return rc;\n    return gcm_tag"),
+    ("gcm_j0_counter", "J0[15] = 1;", "J0[15] = 2;"),
     ("cbc_chains_plaintext", "cipher_block(rk, nr, box, x, out + off);\n        memcpy(chain, out + off, 16);",
      "cipher_block(rk, nr, box, x, out + off);\n        memcpy(chain, in + off, 16);"),
 ]
