@@ -245,7 +245,7 @@ __device__ void bitslice_tile(const TileJob &j)
         bs_ctr_batch<NR>(rk, j.in, j.out, j.nfull, j.tail, w0, w1, w2, j.ctr0, c);
 }
 
-__global__ __launch_bounds__(256) void batched_bitslice_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void batched_bitslice_kernel(
     const aes_segment_t *__restrict__ segs, uint32_t nsegs,
     const aes_key_schedule_t *__restrict__ ks_table, const uint8_t *in_base,
     uint8_t *out_base, void *ws)

@@ -24,7 +24,7 @@ __device__ void ctr_body(const uint32_t *__restrict__ rk, const u32x4 *__restric
         bs_ctr_batch<NR>(rk, in, out, nfull, tail, w0, w1, w2, ctr0, batch * 2048u);
 }
 
-__global__ __launch_bounds__(256) void ctr_bitslice_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void ctr_bitslice_kernel(
     const aes_key_schedule_t *__restrict__ ks, const u32x4 *__restrict__ in,
     u32x4 *__restrict__ out, uint64_t nbytes, uint32_t n0, uint32_t n1, uint32_t n2,
     uint32_t ctr0)
@@ -78,7 +78,7 @@ __device__ void ecb_body(const uint32_t *__restrict__ rk, const u32x4 *__restric
 }
 
 template <bool DEC>
-__global__ __launch_bounds__(256) void ecb_bitslice_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void ecb_bitslice_kernel(
     const aes_key_schedule_t *__restrict__ ks, const u32x4 *__restrict__ in,
     u32x4 *__restrict__ out, uint64_t nblocks)
 {

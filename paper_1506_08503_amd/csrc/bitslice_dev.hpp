@@ -116,7 +116,8 @@ __device__ __forceinline__ void inv_sub_shift(const uint32_t *p, uint32_t *q)
     }
 }
 
-// p = MixColumns(q) + key, key words k[0..3] (one per column).
+// p = MixColumns(q) + key, key words k[0..3] (one per column).  Every output
+// plane is a 4- or 5-term XOR: two three-input XORs.
 __device__ __forceinline__ void mix_add(const uint32_t *q, uint32_t *p, const uint32_t *k)
 {
 #pragma unroll
@@ -134,12 +135,20 @@ __device__ __forceinline__ void mix_add(const uint32_t *q, uint32_t *p, const ui
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const uint32_t *e = d[r];
-            // x * e modulo 0x11B, plane by plane
-            const uint32_t xt[8] = {e[7], e[0] ^ e[7], e[1], e[2] ^ e[7],
-                                    e[3] ^ e[7], e[4], e[5], e[6]};
+            // x * e modulo 0x11B: plane i takes e[i-1], and e[7] too for i in {0, 1, 3, 4}
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                p[32 * c + 8 * r + i] = xor3(xt[i], s[i], a[8 * r + i]) ^ bitmask(k[c], 8 * r + i);
+            for (int i = 0; i < 8; ++i) {
+                const uint32_t m = bitmask(k[c], 8 * r + i);
+                const uint32_t ai = a[8 * r + i];
+                uint32_t v;
+                if (i == 0)
+                    v = xor3(e[7], s[0], ai) ^ m;
+                else if (i == 1 || i == 3 || i == 4)
+                    v = xor3(xor3(e[i - 1], e[7], s[i]), ai, m);
+                else
+                    v = xor3(e[i - 1], s[i], ai) ^ m;
+                p[32 * c + 8 * r + i] = v;
+            }
         }
     }
 }

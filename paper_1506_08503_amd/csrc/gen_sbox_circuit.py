@@ -138,10 +138,11 @@ def mat_inverse(rows):
 class Circuit:
     """Gates over named wires; wire values are 'x0'..'x7' inputs or t<k>."""
 
-    def __init__(self):
+    def __init__(self, rng=None):
         self.gates = []      # (dst, op, a, b)
         self.n = 0
         self.cache = {}
+        self.rng = rng       # random tie-breaking in linear() when given
 
     def new(self, op, a, b):
         key = (op, min(a, b), max(a, b))
@@ -181,7 +182,9 @@ class Circuit:
                     counts[p] = counts.get(p, 0) + 1
             if not counts:
                 break
-            (i, j), _ = max(counts.items(), key=lambda kv: (kv[1], -kv[0][0], -kv[0][1]))
+            top = max(counts.values())
+            best = sorted(p for p, v in counts.items() if v == top)
+            (i, j) = best[self.rng.randrange(len(best))] if self.rng else best[0]
             w = self.xor(wires[i], wires[j])
             wires.append(w)
             k = len(wires) - 1
@@ -207,7 +210,7 @@ def affine_lin(v):
     return s
 
 
-def build(n, m, beta, inverse=False):
+def build(n, m, beta, inverse=False, rng=None):
     """Circuit for one (N, M, beta) choice computing
          forward:  L(inv(x))       = S(x) ^ 0x63
          inverse:  inv(L^-1(y))    = S^-1(y ^ 0x63)
@@ -234,7 +237,7 @@ def build(n, m, beta, inverse=False):
         # output map: tower bits -> AES bits -> affine (without the constant)
         Yrows = mat_from_fn(lambda v: affine_lin(mat_apply(Xinv, v)))
 
-    c = Circuit()
+    c = Circuit(rng)
     xin = ["x%d" % i for i in range(8)]
 
     # Tower bits of the input as linear forms over the 8 input bits; all the
@@ -399,6 +402,83 @@ def build(n, m, beta, inverse=False):
     return c, outs
 
 
+# --------------------------------------------------------------- gate fusion
+# gfx950's v_bitop3_b32 computes any boolean function of three 32-bit
+# operands: result bit = bit (4 a + 2 b + c) of an 8-bit table.  A gate whose
+# only use is another gate can be folded into that gate when the pair reads at
+# most three distinct wires.
+TT_A, TT_B, TT_C = 0xF0, 0xCC, 0xAA
+
+
+def fuse(c, outs):
+    """Returns fused ops [(dst, leaves(list of 1..3 wires), expr)] in order,
+    where expr is a nested tuple over the leaves; inlined gates disappear."""
+    gates = {dst: (op, a, b) for dst, op, a, b in c.gates}
+    uses = {}
+    for dst, op, a, b in c.gates:
+        for w in (a, b):
+            uses[w] = uses.get(w, 0) + 1
+    for o in outs:
+        uses[o] = uses.get(o, 0) + 1
+    inlined = set()
+    exprs = {}
+
+    def leaves_of(e, acc):
+        if isinstance(e, str):
+            if e not in acc:
+                acc.append(e)
+        else:
+            leaves_of(e[1], acc)
+            leaves_of(e[2], acc)
+        return acc
+
+    order = [dst for dst, _, _, _ in c.gates]
+    for dst in order:
+        op, a, b = gates[dst]
+        e = (op, a, b)
+        for side in (1, 2):
+            child = e[side]
+            if child in gates and uses.get(child, 0) == 1 and child not in outs:
+                cand = list(e)
+                cand[side] = exprs[child]
+                cand = tuple(cand)
+                if len(leaves_of(cand, [])) <= 3:
+                    e = cand
+                    inlined.add(child)
+        exprs[dst] = e
+    fused = []
+    for dst in order:
+        if dst in inlined:
+            continue
+        e = exprs[dst]
+        fused.append((dst, leaves_of(e, []), e))
+    return fused
+
+
+def eval_expr(e, env):
+    if isinstance(e, str):
+        return env[e]
+    op, a, b = e
+    va, vb = eval_expr(a, env), eval_expr(b, env)
+    return va ^ vb if op == "^" else va & vb
+
+
+def truth_table(e, leaves):
+    """8-bit table of e with leaves[0..2] as the three bitop3 operands."""
+    env = dict(zip(leaves, (TT_A, TT_B, TT_C)))
+    return eval_expr(e, env) & 0xFF
+
+
+def evaluate_fused(fused, outs, x):
+    """Evaluate the fused op list with bitop3 semantics (bit-serial, one input)."""
+    val = {"x%d" % i: (x >> i) & 1 for i in range(8)}
+    for dst, leaves, e in fused:
+        tt = truth_table(e, leaves)
+        bits = [val[w] for w in leaves] + [0] * (3 - len(leaves))
+        val[dst] = (tt >> (4 * bits[0] + 2 * bits[1] + bits[2])) & 1
+    return sum(val[o] << i for i, o in enumerate(outs))
+
+
 def evaluate(c, outs, x):
     val = {"x%d" % i: (x >> i) & 1 for i in range(8)}
     for dst, op, a, b in c.gates:
@@ -407,7 +487,8 @@ def evaluate(c, outs, x):
     return sum(val[o] << i for i, o in enumerate(outs))
 
 
-def search(target, inverse):
+def search(target, inverse, trials=1):
+    import random
     best = None
     for n in (2, 3):                     # W, W^2 (trace 1 in GF(4))
         if trace(n, gf4_mul, 2) != 1:
@@ -423,30 +504,49 @@ def search(target, inverse):
                     pw.append(mul(pw[-1], beta))
                 if pw[8] ^ pw[4] ^ pw[3] ^ pw[1] ^ pw[0]:
                     continue
-                res = build(n, m, beta, inverse)
-                if res is None:
-                    continue
-                c, outs = res
-                if any(evaluate(c, outs, x) != target[x] for x in range(256)):
-                    raise SystemExit("circuit mismatch for N=%d M=%d beta=%d" % (n, m, beta))
-                ngates = len(c.gates)
-                nand = sum(1 for g in c.gates if g[1] == "&")
-                if best is None or ngates < best[0]:
-                    best = (ngates, nand, n, m, beta, c, outs)
+                for trial in range(trials):
+                    rng = random.Random(trial * 7919 + beta) if trial else None
+                    res = build(n, m, beta, inverse, rng)
+                    if res is None:
+                        break
+                    best = consider(best, res, target, n, m, beta)
+    return best
+
+
+def consider(best, res, target, n, m, beta):
+    """Check one candidate circuit on all 256 inputs (plain and fused) and keep
+    it if its fused op count is the lowest so far."""
+    c, outs = res
+    if any(evaluate(c, outs, x) != target[x] for x in range(256)):
+        raise SystemExit("circuit mismatch for N=%d M=%d beta=%d" % (n, m, beta))
+    fused = fuse(c, outs)
+    if any(evaluate_fused(fused, outs, x) != target[x] for x in range(256)):
+        raise SystemExit("fused circuit mismatch for N=%d M=%d beta=%d" % (n, m, beta))
+    nops = len(fused)
+    nand = sum(1 for g in c.gates if g[1] == "&")
+    if best is None or (nops, len(c.gates)) < (best[0], best[7]):
+        best = (nops, nand, n, m, beta, fused, outs, len(c.gates))
     return best
 
 
 def emit(name, what, best):
-    ngates, nand, n, m, beta, c, outs = best
+    nops, nand, n, m, beta, fused, outs, ngates = best
     lines = ["// %s: tower field GF(((2^2)^2)^2), N=%d M=%d beta=0x%02x;"
              % (what, n, m, beta),
-             "// %d gates (%d AND, %d XOR).  Checked on all 256 inputs by the generator."
-             % (ngates, nand, ngates - nand),
+             "// %d gates (%d AND) fused into %d VALU ops (two-input XOR/AND or one"
+             % (ngates, nand, nops),
+             "// three-input v_bitop3_b32 each).  Checked on all 256 inputs by the generator.",
              "#define %s(x0, x1, x2, x3, x4, x5, x6, x7, y0, y1, y2, y3, y4, y5, y6, y7) \\"
              % name,
              "    do { \\"]
-    for dst, op, a, b in c.gates:
-        lines.append("        const uint32_t %s = %s %s %s; \\" % (dst, a, op, b))
+    for dst, leaves, e in fused:
+        if isinstance(e[1], str) and isinstance(e[2], str):
+            rhs = "%s %s %s" % (e[1], e[0], e[2])
+        else:
+            ops = leaves + ["0u"] * (3 - len(leaves))
+            rhs = "__builtin_amdgcn_bitop3_b32(%s, %s, %s, 0x%02x)" % (
+                ops[0], ops[1], ops[2], truth_table(e, leaves))
+        lines.append("        const uint32_t %s = %s; \\" % (dst, rhs))
     for i, o in enumerate(outs):
         lines.append("        y%d = %s; \\" % (i, o))
     lines.append("    } while (0)")
@@ -458,8 +558,9 @@ def main():
     inv_sbox = [0] * 256
     for x, y in enumerate(sbox):
         inv_sbox[y] = x
-    fwd = search([sbox[x] ^ 0x63 for x in range(256)], False)
-    inv = search([inv_sbox[y ^ 0x63] for y in range(256)], True)
+    trials = int(os.environ.get("SBOX_SEARCH_TRIALS", "6"))
+    fwd = search([sbox[x] ^ 0x63 for x in range(256)], False, trials)
+    inv = search([inv_sbox[y ^ 0x63] for y in range(256)], True, trials)
     lines = ["// Generated by gen_sbox_circuit.py -- do not edit.",
              "// Bitsliced AES S-boxes with the affine constant 0x63 left out (the",
              "// kernels fold it into the round keys).  Inputs x0..x7 and outputs",
@@ -469,7 +570,8 @@ def main():
     with open(OUT, "w") as f:
         f.write("\n".join(lines) + "\n")
     for tag, b in (("forward", fwd), ("inverse", inv)):
-        print("%s: %d gates (%d AND), N=%d M=%d beta=0x%02x" % ((tag,) + b[:5]))
+        print("%s: %d fused ops from %d gates (%d AND), N=%d M=%d beta=0x%02x"
+              % (tag, b[0], b[7], b[1], b[2], b[3], b[4]))
 
 
 if __name__ == "__main__":
