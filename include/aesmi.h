@@ -156,6 +156,53 @@ aes_status_t aes_cbc_decrypt(const aes_key_schedule_t *ks_dev, const void *iv_de
                              size_t nmsg, size_t msg_bytes, void *stream);
 
 /*
+ * Galois/Counter Mode, NIST SP 800-38D, with 96-bit IVs.  The paper's modes
+ * (CBC, App. A1; counter mode, sec. II) give confidentiality only; GCM adds a
+ * 128-bit authentication tag over the ciphertext and additional data:
+ *   C = CTR_K(counter blocks IV || 2, IV || 3, ...) applied to P,
+ *   T = E_K(IV || 1) ^ GHASH_H(A || 0-pad || C || 0-pad || len64(A) || len64(C)),
+ *   H = E_K(0^128), GHASH_H(X_1..X_m) = sum_i X_i H^(m-i+1) in GF(2^128) with
+ *   x^128 + x^7 + x^2 + x + 1 (SP 800-38D sec. 6.3-7.1, bit order of sec. 6.3).
+ *   iv          host, 12 bytes (other IV lengths are not supported)
+ *   aad_dev     device, aad_len bytes of additional authenticated data
+ *               (16-byte aligned; NULL allowed when aad_len == 0)
+ *   in_dev/out_dev  device, nbytes each (any nbytes >= 0; in place allowed)
+ *   tag_dev     device, 16 bytes (16-byte aligned): the full 128-bit tag
+ *   ws_dev      device workspace of at least aes_gcm_workspace_bytes(aad_len,
+ *               nbytes) bytes, 256-byte aligned, private to the call until the
+ *               stream has passed it (holds H, E_K(J0), the powers of H and the
+ *               partial GHASH sums).
+ * aes_gcm_decrypt computes the tag over the ciphertext in_dev (before it
+ * writes out_dev, so in place is fine) and deciphers; comparing that tag with
+ * the received one is the caller's step: per SP 800-38D sec. 7.2 the plaintext
+ * must not be released unless they are equal.  Errors: AES_ERR_NULL,
+ * AES_ERR_ALIGN, AES_ERR_OVERLAP, AES_ERR_COUNTER (more than 2^32 - 2 blocks),
+ * AES_ERR_LENGTH (aad_len >= 2^61), AES_ERR_CONFIG (workspace too small).
+ */
+size_t aes_gcm_workspace_bytes(size_t aad_len, size_t nbytes);
+aes_status_t aes_gcm_encrypt(const aes_key_schedule_t *ks_dev, const uint8_t *iv,
+                             const void *aad_dev, size_t aad_len, const void *in_dev,
+                             void *out_dev, size_t nbytes, void *tag_dev, void *ws_dev,
+                             size_t ws_bytes, void *stream);
+aes_status_t aes_gcm_decrypt(const aes_key_schedule_t *ks_dev, const uint8_t *iv,
+                             const void *aad_dev, size_t aad_len, const void *in_dev,
+                             void *out_dev, size_t nbytes, void *tag_dev, void *ws_dev,
+                             size_t ws_bytes, void *stream);
+
+/*
+ * aes_ghash -- GHASH_H over nblocks 16-byte blocks (SP 800-38D Algorithm 2),
+ * the authentication half of GCM on its own.
+ *   h        host, 16 bytes: the hash subkey H
+ *   x_dev    device, nblocks * 16 bytes (16-byte aligned)
+ *   y_dev    device, 16 bytes (16-byte aligned): the result (zero if nblocks == 0)
+ *   ws_dev   device workspace of aes_ghash_workspace_bytes(nblocks) bytes,
+ *            256-byte aligned.
+ */
+size_t aes_ghash_workspace_bytes(size_t nblocks);
+aes_status_t aes_ghash(const uint8_t *h, const void *x_dev, size_t nblocks, void *y_dev,
+                       void *ws_dev, size_t ws_bytes, void *stream);
+
+/*
  * Batched CTR: many messages, each with its own key schedule, nonce and
  * counter, in one persistent launch (the per-row V and K of sec. II applied to
  * messages of uneven length).  Message s reads nbytes bytes at

@@ -9,14 +9,16 @@ continuous-batching request loop on top.
 """
 from .aesmi import (AesError, KeySchedule, Launch, Segment, BatchTune, lib, expand_key,
                     schedule_to_device, key_schedule, expand_keys_device, ecb_encrypt,
-                    ecb_decrypt, ctr_xcrypt, cbc_encrypt, cbc_decrypt, device_cu_count, header_functions,
+                    ecb_decrypt, ctr_xcrypt, cbc_encrypt, cbc_decrypt, gcm_encrypt, gcm_decrypt, ghash,
+                    gcm_workspace_bytes, ghash_workspace_bytes, device_cu_count, header_functions,
                     LAYOUT_AUTO, LAYOUT_TTABLE, LAYOUT_BITSLICE, SCHEDULE_BYTES,
                     SEGMENT_BYTES, STATUS, segment_dtype, batched_workspace_bytes,
                     ctr_xcrypt_batched, batched_read_status, BatchedGraph)
 
 __all__ = ["AesError", "KeySchedule", "Launch", "Segment", "BatchTune", "lib", "expand_key",
            "schedule_to_device", "key_schedule", "expand_keys_device", "ecb_encrypt",
-           "ecb_decrypt", "ctr_xcrypt", "cbc_encrypt", "cbc_decrypt", "device_cu_count", "header_functions",
+           "ecb_decrypt", "ctr_xcrypt", "cbc_encrypt", "cbc_decrypt", "gcm_encrypt", "gcm_decrypt",
+           "ghash", "gcm_workspace_bytes", "ghash_workspace_bytes", "device_cu_count", "header_functions",
            "LAYOUT_AUTO", "LAYOUT_TTABLE", "LAYOUT_BITSLICE", "SCHEDULE_BYTES",
            "SEGMENT_BYTES", "STATUS", "segment_dtype", "batched_workspace_bytes",
            "ctr_xcrypt_batched", "batched_read_status", "BatchedGraph"]

@@ -97,6 +97,11 @@ def lib():
             "aes_ctr_xcrypt_ex": ([vp, vp, u32, vp, vp, sz, ctypes.POINTER(Launch), vp], st),
             "aes_cbc_encrypt": ([vp, vp, sz, vp, vp, sz, sz, vp], st),
             "aes_cbc_decrypt": ([vp, vp, sz, vp, vp, sz, sz, vp], st),
+            "aes_gcm_workspace_bytes": ([sz, sz], sz),
+            "aes_gcm_encrypt": ([vp, vp, vp, sz, vp, vp, sz, vp, vp, sz, vp], st),
+            "aes_gcm_decrypt": ([vp, vp, vp, sz, vp, vp, sz, vp, vp, sz, vp], st),
+            "aes_ghash_workspace_bytes": ([sz], sz),
+            "aes_ghash": ([vp, vp, sz, vp, vp, sz, vp], st),
             "aes_batched_workspace_bytes": ([u32], sz),
             "aes_ctr_xcrypt_batched": ([vp, u32, vp, u32, vp, vp, ctypes.POINTER(BatchTune),
                                         vp, sz, vp], st),
@@ -275,6 +280,93 @@ def cbc_decrypt(ks: torch.Tensor, iv: torch.Tensor, x: torch.Tensor, nmsg: int =
                 out: torch.Tensor | None = None) -> torch.Tensor:
     """aes_cbc_decrypt (out of place)."""
     return _cbc("aes_cbc_decrypt", ks, iv, x, nmsg, out)
+
+
+# ---------------------------------------------------------------------- GCM
+def gcm_workspace_bytes(aad_len: int, nbytes: int) -> int:
+    return int(lib().aes_gcm_workspace_bytes(aad_len, nbytes))
+
+
+def ghash_workspace_bytes(nblocks: int) -> int:
+    return int(lib().aes_ghash_workspace_bytes(nblocks))
+
+
+def _workspace(nbytes: int, device, ws):
+    if ws is None:
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+    _dev_u8(ws, "workspace")
+    if ws.data_ptr() % 256:
+        raise ValueError("workspace must be 256-byte aligned")
+    return ws
+
+
+def _small_out(t, device, name):
+    if t is None:
+        t = torch.empty(16, dtype=torch.uint8, device=device)
+    _dev_u8(t, name)
+    if t.numel() != 16:
+        raise ValueError("%s must hold 16 bytes" % name)
+    return t
+
+
+def _gcm(fname, ks, iv, x, aad, out, tag, ws):
+    _dev_u8(x, "input")
+    iv = bytes(iv)
+    if len(iv) != 12:
+        raise ValueError("iv must be 12 bytes")
+    if aad is None:
+        aad = torch.empty(0, dtype=torch.uint8, device=x.device)
+    elif not isinstance(aad, torch.Tensor):
+        aad = torch.frombuffer(bytearray(bytes(aad)), dtype=torch.uint8).to(x.device) \
+            if len(aad) else torch.empty(0, dtype=torch.uint8, device=x.device)
+    _dev_u8(aad, "aad")
+    out = _out_like(x, out)
+    tag = _small_out(tag, x.device, "tag")
+    need = gcm_workspace_bytes(aad.numel(), x.numel())
+    ws = _workspace(need, x.device, ws)
+    ivb = ctypes.create_string_buffer(iv, 12)
+    with torch.cuda.device(x.device):
+        st = getattr(lib(), fname)(_ks_arg(ks), ivb, _ptr(aad) if aad.numel() else None,
+                                   aad.numel(), _ptr(x), _ptr(out), x.numel(), _ptr(tag),
+                                   _ptr(ws), ws.numel(), _stream(x))
+    _check(st, fname)
+    return out, tag
+
+
+def gcm_encrypt(ks: torch.Tensor, iv: bytes, x: torch.Tensor, aad=None,
+                out: torch.Tensor | None = None, tag: torch.Tensor | None = None,
+                ws: torch.Tensor | None = None):
+    """aes_gcm_encrypt: returns (ciphertext, 16-byte tag), both on the device.
+    aad is a uint8 device tensor or bytes (copied to the device)."""
+    return _gcm("aes_gcm_encrypt", ks, iv, x, aad, out, tag, ws)
+
+
+def gcm_decrypt(ks: torch.Tensor, iv: bytes, x: torch.Tensor, aad=None,
+                out: torch.Tensor | None = None, tag: torch.Tensor | None = None,
+                ws: torch.Tensor | None = None):
+    """aes_gcm_decrypt: returns (plaintext, tag computed over x).  The caller
+    compares the tag with the received one before using the plaintext."""
+    return _gcm("aes_gcm_decrypt", ks, iv, x, aad, out, tag, ws)
+
+
+def ghash(h: bytes, x: torch.Tensor, y: torch.Tensor | None = None,
+          ws: torch.Tensor | None = None) -> torch.Tensor:
+    """aes_ghash: GHASH_H over the 16-byte blocks of x."""
+    _dev_u8(x, "input")
+    h = bytes(h)
+    if len(h) != 16:
+        raise ValueError("h must be 16 bytes")
+    if x.numel() % 16:
+        raise ValueError("input must be whole 16-byte blocks")
+    nblocks = x.numel() // 16
+    y = _small_out(y, x.device, "y")
+    ws = _workspace(ghash_workspace_bytes(nblocks), x.device, ws)
+    hb = ctypes.create_string_buffer(h, 16)
+    with torch.cuda.device(x.device):
+        st = lib().aes_ghash(hb, _ptr(x) if nblocks else None, nblocks, _ptr(y), _ptr(ws),
+                             ws.numel(), _stream(x))
+    _check(st, "aes_ghash")
+    return y
 
 
 # ------------------------------------------------------------------- batched

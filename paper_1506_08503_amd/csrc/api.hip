@@ -233,6 +233,83 @@ aes_status_t aes_cbc_decrypt(const aes_key_schedule_t *ks_dev, const void *iv_de
     return cbc_common(true, ks_dev, iv_dev, iv_stride, in_dev, out_dev, nmsg, msg_bytes, stream);
 }
 
+static bool aligned256(const void *p)
+{
+    return (reinterpret_cast<uintptr_t>(p) & 255u) == 0;
+}
+
+static uint32_t le_word(const uint8_t *b)
+{
+    return (uint32_t)b[0] | ((uint32_t)b[1] << 8) | ((uint32_t)b[2] << 16) |
+           ((uint32_t)b[3] << 24);
+}
+
+size_t aes_gcm_workspace_bytes(size_t aad_len, size_t nbytes)
+{
+    return gcm_workspace_bytes(aad_len, nbytes);
+}
+
+static aes_status_t gcm_common(bool decrypt, const aes_key_schedule_t *ks, const uint8_t *iv,
+                               const void *aad, size_t aad_len, const void *in, void *out,
+                               size_t nbytes, void *tag, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ks || !iv || !tag || !ws || (nbytes && (!in || !out)) || (aad_len && !aad))
+        return AES_ERR_NULL;
+    if (aad_len >= (1ull << 61))
+        return AES_ERR_LENGTH;
+    if (!aligned16(tag) || !aligned256(ws) || (nbytes && (!aligned16(in) || !aligned16(out))) ||
+        (aad_len && !aligned16(aad)))
+        return AES_ERR_ALIGN;
+    if (nbytes && bad_overlap(in, out, nbytes))
+        return AES_ERR_OVERLAP;
+    // counter blocks 2 .. 2 + ceil(n / 16) - 1 must not wrap (SP 800-38D sec. 5.2.1.1)
+    if (((uint64_t)nbytes + 15u) / 16u + 2u > (1ull << 32))
+        return AES_ERR_COUNTER;
+    if (ws_bytes < gcm_workspace_bytes(aad_len, nbytes))
+        return AES_ERR_CONFIG;
+    const uint32_t ivw[3] = {le_word(iv), le_word(iv + 4), le_word(iv + 8)};
+    return from_hip(gcm(decrypt, ks, ivw, aad, aad_len, in, out, nbytes, tag, ws,
+                        static_cast<hipStream_t>(stream)));
+}
+
+aes_status_t aes_gcm_encrypt(const aes_key_schedule_t *ks_dev, const uint8_t *iv,
+                             const void *aad_dev, size_t aad_len, const void *in_dev,
+                             void *out_dev, size_t nbytes, void *tag_dev, void *ws_dev,
+                             size_t ws_bytes, void *stream)
+{
+    return gcm_common(false, ks_dev, iv, aad_dev, aad_len, in_dev, out_dev, nbytes, tag_dev,
+                      ws_dev, ws_bytes, stream);
+}
+
+aes_status_t aes_gcm_decrypt(const aes_key_schedule_t *ks_dev, const uint8_t *iv,
+                             const void *aad_dev, size_t aad_len, const void *in_dev,
+                             void *out_dev, size_t nbytes, void *tag_dev, void *ws_dev,
+                             size_t ws_bytes, void *stream)
+{
+    return gcm_common(true, ks_dev, iv, aad_dev, aad_len, in_dev, out_dev, nbytes, tag_dev,
+                      ws_dev, ws_bytes, stream);
+}
+
+size_t aes_ghash_workspace_bytes(size_t nblocks)
+{
+    return ghash_workspace_bytes(nblocks);
+}
+
+aes_status_t aes_ghash(const uint8_t *h, const void *x_dev, size_t nblocks, void *y_dev,
+                       void *ws_dev, size_t ws_bytes, void *stream)
+{
+    if (!h || !y_dev || !ws_dev || (nblocks && !x_dev))
+        return AES_ERR_NULL;
+    if (!aligned16(y_dev) || !aligned256(ws_dev) || (nblocks && !aligned16(x_dev)))
+        return AES_ERR_ALIGN;
+    if (nblocks > (1ull << 40))
+        return AES_ERR_LENGTH;
+    if (ws_bytes < ghash_workspace_bytes(nblocks))
+        return AES_ERR_CONFIG;
+    const uint32_t hw[4] = {le_word(h), le_word(h + 4), le_word(h + 8), le_word(h + 12)};
+    return from_hip(ghash(hw, x_dev, nblocks, y_dev, ws_dev, static_cast<hipStream_t>(stream)));
+}
+
 size_t aes_batched_workspace_bytes(uint32_t nsegs)
 {
     return batched_workspace_bytes(nsegs);

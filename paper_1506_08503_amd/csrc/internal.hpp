@@ -39,6 +39,15 @@ hipError_t bitslice_ctr(const aes_key_schedule_t *ks, const uint32_t nonce_words
 hipError_t cbc(bool decrypt, const aes_key_schedule_t *ks, const void *iv, uint32_t iv_step,
                const void *in, void *out, uint64_t nmsg, uint64_t nblk, hipStream_t stream);
 
+// --- Galois/Counter Mode and GHASH (gcm.hip) --------------------------------
+size_t gcm_workspace_bytes(uint64_t aad_len, uint64_t nbytes);
+size_t ghash_workspace_bytes(uint64_t nblocks);
+hipError_t gcm(bool decrypt, const aes_key_schedule_t *ks, const uint32_t iv_words[3],
+               const void *aad, uint64_t aad_len, const void *in, void *out, uint64_t nbytes,
+               void *tag, void *ws, hipStream_t stream);
+hipError_t ghash(const uint32_t h_words[4], const void *x, uint64_t nblocks, void *y, void *ws,
+                 hipStream_t stream);
+
 // --- device key expansion (keyexp.hip) -------------------------------------
 hipError_t expand_keys_device(const uint8_t *keys, uint32_t key_bytes, uint64_t nkeys,
                               aes_key_schedule_t *ks, hipStream_t stream);

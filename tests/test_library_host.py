@@ -151,3 +151,33 @@ def test_binding_rejects_cpu_tensors():
         am.ctr_xcrypt(x, b"n" * 12, 0, x)
     with pytest.raises(TypeError):
         am.ecb_encrypt(x, x)
+
+
+def test_gcm_and_ghash_validation():
+    ks, iv, a, b = VP(0x10000), ctypes.create_string_buffer(12), VP(0x20000), VP(0x40000)
+    tag, ws, aad = VP(0x60000), VP(0x100000), VP(0x70000)
+    need = L.aes_gcm_workspace_bytes(0, 64)
+    assert need >= 256 and L.aes_gcm_workspace_bytes(16, 1 << 30) > need
+    for f in (L.aes_gcm_encrypt, L.aes_gcm_decrypt):
+        assert f(None, iv, None, 0, a, b, 64, tag, ws, need, None) == -1
+        assert f(ks, None, None, 0, a, b, 64, tag, ws, need, None) == -1
+        assert f(ks, iv, None, 0, a, b, 64, None, ws, need, None) == -1
+        assert f(ks, iv, None, 0, a, b, 64, tag, None, need, None) == -1
+        assert f(ks, iv, None, 16, a, b, 64, tag, ws, need, None) == -1     # aad missing
+        assert f(ks, iv, None, 0, None, b, 64, tag, ws, need, None) == -1
+        assert f(ks, iv, None, 0, VP(0x20004), b, 64, tag, ws, need, None) == -4
+        assert f(ks, iv, VP(0x70001), 3, a, b, 64, tag, ws, need, None) == -4
+        assert f(ks, iv, None, 0, a, b, 64, VP(0x60008), ws, need, None) == -4
+        assert f(ks, iv, None, 0, a, b, 64, tag, VP(0x100080), need, None) == -4
+        assert f(ks, iv, None, 0, a, VP(0x20010), 64, tag, ws, need, None) == -5
+        assert f(ks, iv, None, 0, a, b, 64, tag, ws, need - 1, None) == -9
+        assert f(ks, iv, aad, 1 << 61, a, b, 64, tag, ws, need, None) == -3
+        # at most 2^32 - 2 blocks (counters 2 .. 2^32 - 1)
+        big = (2 ** 32 - 1) * 16
+        assert f(ks, iv, None, 0, VP(1 << 44), VP(1 << 45), big, tag, ws, 1 << 40, None) == -6
+    h = ctypes.create_string_buffer(16)
+    gneed = L.aes_ghash_workspace_bytes(100)
+    assert L.aes_ghash(None, a, 100, tag, ws, gneed, None) == -1
+    assert L.aes_ghash(h, None, 100, tag, ws, gneed, None) == -1
+    assert L.aes_ghash(h, VP(0x20008), 100, tag, ws, gneed, None) == -4
+    assert L.aes_ghash(h, a, 100, tag, ws, gneed - 1, None) == -9
