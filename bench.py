@@ -11,6 +11,9 @@ Besides the throughput it reports
   * roofline: HBM-roofline position of the CTR kernel (algorithmic bytes = 16 B
     read + 16 B written per block, divided by the kernel's average duration
     from HIP events on the launch stream), plus the binding on-chip limits;
+  * gcm: AES-128-GCM over the same buffer (encrypt, decrypt) and the GHASH
+    passes alone, with their HBM and LDS fractions;
+  * batched / serving: many-message launches and the request loop;
   * cpu_baseline: the CPU oracle (plain algebraic AES) timed on the host's
     cores over a bounded sample of the same workload.
 """
@@ -39,7 +42,8 @@ def parse():
     p.add_argument("--nbytes", type=int, default=4 << 30)
     p.add_argument("--layout", choices=["auto", "ttable", "bitslice"], default="auto")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--op", choices=["ctr", "ecb-enc", "ecb-dec"], default="ctr",
+    p.add_argument("--op", choices=["ctr", "ecb-enc", "ecb-dec", "gcm-enc", "gcm-dec"],
+                   default="ctr",
                    help="operation of the stream leg (the headline metric is ctr)")
     p.add_argument("--key-bytes", type=int, default=16, choices=[16, 24, 32])
     p.add_argument("--mode", choices=["aes", "copy"], default="aes",
@@ -47,6 +51,7 @@ def parse():
                         "(reference for HBM counter calibration)")
     p.add_argument("--cpu-threads", type=int, default=0)
     p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--no-gcm", action="store_true")
     p.add_argument("--no-serving", action="store_true")
     p.add_argument("--serving-requests", type=int, default=100_000)
     p.add_argument("--sweep", action="store_true",
@@ -175,6 +180,44 @@ def sweep_fig3():
     return {"sweep": "paper Fig. 3 workloads, AES-128", "rows": rows}
 
 
+def _event_ms(torch, fn, steps, warmup=2):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def gcm_leg(am, ks, iv, x, y, steps=10):
+    """AES-GCM (SP 800-38D) over the same resident buffer: encryption,
+    decryption, and GHASH alone.  The wide GHASH pass reads 16 B per block and
+    makes 16 ds_read_b128 + 14 ds_read_b32 (78 dword reads) per block."""
+    import torch
+    n = x.numel()
+    nblocks = n // 16
+    ws = torch.empty(am.gcm_workspace_bytes(0, n), dtype=torch.uint8, device=x.device)
+    tag = torch.empty(16, dtype=torch.uint8, device=x.device)
+    enc = _event_ms(torch, lambda: am.gcm_encrypt(ks, iv, x, out=y, tag=tag, ws=ws), steps)
+    dec = _event_ms(torch, lambda: am.gcm_decrypt(ks, iv, y, out=x, tag=tag, ws=ws), steps)
+    gws = torch.empty(am.ghash_workspace_bytes(nblocks), dtype=torch.uint8, device=x.device)
+    h = bytes(range(16))
+    gh = _event_ms(torch, lambda: am.ghash(h, y, y=tag, ws=gws), steps)
+    lds = 78 * nblocks / (gh * 1e-3) / 1e12
+    return {"workload": "aes128-gcm-%dMiB" % (n >> 20), "aad_bytes": 0,
+            "enc_GBps": round(n / (enc * 1e-3) / 1e9, 1), "enc_ms": round(enc, 4),
+            "dec_GBps": round(n / (dec * 1e-3) / 1e9, 1), "dec_ms": round(dec, 4),
+            "ghash_ms": round(gh, 4), "ghash_GBps": round(n / (gh * 1e-3) / 1e9, 1),
+            "ghash_hbm_frac": round(n / (gh * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "ghash_lds_frac_at_2p4ghz": round(lds / LDS_PEAK_TREADS, 4),
+            "kernel": "ghash_pass_wide_kernel"}
+
+
 def load_traffic(path, kernel):
     try:
         with open(path) as f:
@@ -197,6 +240,9 @@ def main():
     if args.sweep:
         print(json.dumps(sweep_fig3()), flush=True)
         return
+    if args.op.startswith("gcm") and args.layout == "bitslice":
+        print("GCM runs on the table kernels (--layout auto|ttable)", file=sys.stderr)
+        sys.exit(2)
     layout = {"auto": am.LAYOUT_AUTO, "ttable": am.LAYOUT_TTABLE,
               "bitslice": am.LAYOUT_BITSLICE}[args.layout]
     inp = wl.stream_inputs(wl.SEED_STREAM, args.nbytes, key_bytes=args.key_bytes)
@@ -208,6 +254,9 @@ def main():
     y = torch.empty_like(x)
     ks = am.key_schedule(inp.key, dev)
     kw = {} if layout == am.LAYOUT_AUTO else {"layout": layout}
+    if args.op.startswith("gcm"):
+        gws = torch.empty(am.gcm_workspace_bytes(0, inp.nbytes), dtype=torch.uint8, device=dev)
+        gtag = torch.empty(16, dtype=torch.uint8, device=dev)
 
     def step():
         if args.mode == "copy":
@@ -216,6 +265,10 @@ def main():
             am.ecb_encrypt(ks, x, out=y, **kw)
         elif args.op == "ecb-dec":
             am.ecb_decrypt(ks, x, out=y, **kw)
+        elif args.op == "gcm-enc":
+            am.gcm_encrypt(ks, inp.nonce, x, out=y, tag=gtag, ws=gws)
+        elif args.op == "gcm-dec":
+            am.gcm_decrypt(ks, inp.nonce, x, out=y, tag=gtag, ws=gws)
         else:
             am.ctr_xcrypt(ks, inp.nonce, inp.ctr0, x, out=y, **kw)
 
@@ -245,8 +298,10 @@ def main():
                    ("ecb-enc", False): "ecb_ttable_kernel<false, 4>",
                    ("ecb-enc", True): "ecb_bitslice_kernel<false>",
                    ("ecb-dec", False): "ecb_ttable_kernel<true, 4>",
-                   ("ecb-dec", True): "ecb_bitslice_kernel<true>"}[(args.op,
-                                                                    args.layout == "bitslice")]
+                   ("ecb-dec", True): "ecb_bitslice_kernel<true>",
+                   ("gcm-enc", False): "gcm step (ctr_grouped_kernel + ghash passes)",
+                   ("gcm-dec", False): "gcm step (ghash passes + ctr_grouped_kernel)"}[
+                       (args.op, args.layout == "bitslice")]
     # counters were taken for the default workload only (AES-128 CTR, 4 GiB)
     default_cfg = (args.op, args.key_bytes, args.nbytes, args.layout) == ("ctr", 16, 4 << 30,
                                                                            "auto")
@@ -255,7 +310,7 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": kernel_name,
                 "kernel_ms_avg": round(avg_ms, 4), "kernel_ms_min": round(min(kernel_ms), 4)}
-    if args.layout != "bitslice":
+    if args.layout != "bitslice" and not args.op.startswith("gcm"):
         # On-chip limit of the table kernels: LDS reads per block -- CTR:
         # 16 (Nr - 2) (rounds 1-2 come from per-thread and per-256-counter
         # group precomputation); ECB: 16 Nr -- against 32 reads/clk/CU.
@@ -283,6 +338,8 @@ def main():
                       "nbytes": inp.nbytes,
                       "blocks": nblocks, "layout": args.layout, "in_place": False},
            "roofline": roofline}
+    if not args.no_gcm and default_cfg:
+        out["gcm"] = gcm_leg(am, ks, inp.nonce, x, y)
     del x, y
     torch.cuda.empty_cache()
     if not args.no_batched:

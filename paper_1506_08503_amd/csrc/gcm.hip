@@ -12,13 +12,17 @@
 //
 // Multiplication by a fixed G uses 8-bit tables (Shoup's method): with M[b] =
 // b(x) * G for every byte value b, Y * G = sum_k x^(8k) M[Y_k], evaluated by
-// Horner from the top byte: acc <- acc * x^8 ^ M[Y_k].  Multiplying by x^8 is
-// a byte shift of the raw words plus one 256-entry reduction table R[o] for
-// the byte o that leaves the top.  Both tables live in LDS, replicated so that
-// lanes never share a bank: M as 16 copies of 16 bytes per entry (address
-// b << 8 | copy << 4, one ds_read_b128), R as 64 copies of one word (address
-// 0x10000 | o << 8 | lane << 2).  Each address is one v_perm_b32 of the data
-// word with a per-lane constant.  128 KiB per workgroup.
+// Horner from the top byte.  Multiplying the accumulator by x^8 is a byte
+// shift of the raw words plus a 256-entry reduction table R[o] for the byte o
+// that leaves the top.  The wide passes take two bytes per step with a second
+// table M'[b] = b(x) x^8 G: acc <- acc * x^16 ^ M'[Y_(2q+1)] ^ M[Y_2q], two R
+// lookups per step (about 110 VALU ops and 16 + 14 LDS reads per block).
+// The tables live in LDS, replicated so that lanes never share a bank, each
+// address one v_perm_b32 of a data word with a per-lane constant:
+//   M, M'  256 entries x 8 copies x 16 B, interleaved (b << 8 | t << 7 | c << 4)
+//   R      256 entries x 64 copies x 4 B at 0x10000 (o << 8 | lane << 2)
+// 128 KiB per workgroup.  Narrow passes and the final wave use one copy of a
+// one-byte-step table.
 //
 // Parallel GHASH.  Pad the sequence with zeros in front to T * J blocks (a
 // leading zero block does not change GHASH).  Virtual lane g in [0, T) takes
@@ -40,7 +44,7 @@ namespace {
 
 constexpr uint32_t kMaxPow = 32;
 constexpr uint64_t kMaxT = 1ull << 19;       // virtual lanes of the widest pass
-constexpr uint64_t kMainMinT = 1ull << 16;   // passes this wide use the replicated tables
+constexpr uint64_t kWideMinT = 1ull << 16;   // passes this wide use the replicated tables
 constexpr uint32_t kFinalN = 64;             // the final wave combines <= 64 values
 
 struct GcmHdr {
@@ -139,36 +143,46 @@ __device__ __forceinline__ uint32_t reduce_entry(uint32_t o)
 }
 
 // ------------------------------------------------------------ table layouts
-// Replicated, bank-conflict-free layout for wide passes (128 KiB).
-struct MainLayout {
+// Replicated, bank-conflict-free layout for wide passes (128 KiB), two bytes
+// per Horner step: M0[b] = b(x) G and M1[b] = b(x) x^8 G interleaved, 8
+// copies of 16 bytes each (entry b, table t, copy c at b << 8 | t << 7 |
+// c << 4: eight consecutive lanes read eight distinct 16-byte bank groups),
+// then R with 64 copies of one word at 0x10000 | o << 8 | lane << 2.
+struct WideLayout {
     static constexpr uint32_t kLds = 0x20000u;
-    uint32_t cm, cr;
+    uint32_t c0, c1, cr;
 
-    __device__ explicit MainLayout(uint32_t tid)
-        : cm((tid & 15u) << 4), cr(0x10000u | ((tid & 63u) << 2))
+    __device__ explicit WideLayout(uint32_t tid)
+        : c0((tid & 7u) << 4), c1(0x80u | ((tid & 7u) << 4)), cr(0x10000u | ((tid & 63u) << 2))
     {
     }
 
-    template <int K>
+    // entry (byte K of w) of M_T
+    template <int T, int K>
     __device__ __forceinline__ u32x4 m(const char *lds, uint32_t w) const
     {
-        const uint32_t a = __builtin_amdgcn_perm(w, cm, 0x0c020000u | ((4u + K) << 8));
+        const uint32_t a = __builtin_amdgcn_perm(w, T ? c1 : c0, 0x0c020000u | ((4u + K) << 8));
         return *reinterpret_cast<const u32x4 *>(lds + a);
     }
 
-    __device__ __forceinline__ uint32_t r(const char *lds, uint32_t w3) const
+    // R[byte K of w]
+    template <int K>
+    __device__ __forceinline__ uint32_t r(const char *lds, uint32_t w) const
     {
-        const uint32_t a = __builtin_amdgcn_perm(w3, cr, 0x0c020700u);
+        const uint32_t a = __builtin_amdgcn_perm(w, cr, 0x0c020000u | ((4u + K) << 8));
         return *reinterpret_cast<const uint32_t *>(lds + a);
     }
 
     __device__ static void fill(char *lds, const u32x4 &g)
     {
-        V4 b[8];
-        basis8(g, b);
-        for (uint32_t e = threadIdx.x; e < 256u * 16u; e += blockDim.x) {
-            const uint32_t idx = e >> 4, c = e & 15u;
-            *reinterpret_cast<u32x4 *>(lds + (idx << 8) + (c << 4)) = table_entry(b, idx);
+        V4 b0[8], b1[8];
+        basis8(g, b0);
+        V4 g8 = mul_x(b0[7]);
+        basis8(u32x4{g8.w[0], g8.w[1], g8.w[2], g8.w[3]}, b1);
+        for (uint32_t e = threadIdx.x; e < 256u * 2u * 8u; e += blockDim.x) {
+            const uint32_t idx = e >> 4, t = (e >> 3) & 1u, c = e & 7u;
+            *reinterpret_cast<u32x4 *>(lds + (idx << 8) + (t << 7) + (c << 4)) =
+                t ? table_entry(b1, idx) : table_entry(b0, idx);
         }
         for (uint32_t e = threadIdx.x; e < 256u * 64u; e += blockDim.x) {
             const uint32_t o = e >> 6, l = e & 63u;
@@ -176,6 +190,52 @@ struct MainLayout {
         }
     }
 };
+
+// y <- y * G ^ x with the wide layout: Y * G = sum_q x^(16q) (M1[Y_(2q+1)] ^
+// M0[Y_2q]) by Horner over q; acc * x^16 shifts the raw words by two bytes and
+// folds the two bytes that leave the top: byte 14 lands on x^128.. (R[o14] in
+// bytes 0-1), byte 15 on x^136.. (R[o15] one byte higher).
+template <int Q>
+__device__ __forceinline__ void wide_pair(const char *lds, const WideLayout &lay,
+                                          const uint32_t (&y)[4], u32x4 &m1, u32x4 &m0)
+{
+    m1 = lay.template m<1, (2 * Q + 1) & 3>(lds, y[(2 * Q + 1) >> 2]);
+    m0 = lay.template m<0, (2 * Q) & 3>(lds, y[(2 * Q) >> 2]);
+}
+
+__device__ __forceinline__ void gmul_wide(uint32_t (&y)[4], const uint32_t (&x)[4],
+                                          const char *lds, const WideLayout &lay)
+{
+    u32x4 m1, m0;
+    wide_pair<7>(lds, lay, y, m1, m0);
+    uint32_t a0 = m1.x ^ m0.x, a1 = m1.y ^ m0.y, a2 = m1.z ^ m0.z, a3 = m1.w ^ m0.w;
+#define AESMI_WSTEP(Q)                                                              \
+    do {                                                                            \
+        const uint32_t ra = lay.template r<2>(lds, a3);                             \
+        const uint32_t rb = lay.template r<3>(lds, a3) << 8;                        \
+        wide_pair<Q>(lds, lay, y, m1, m0);                                          \
+        const uint32_t n3 = __builtin_amdgcn_alignbyte(a3, a2, 2);                  \
+        const uint32_t n2 = __builtin_amdgcn_alignbyte(a2, a1, 2);                  \
+        const uint32_t n1 = __builtin_amdgcn_alignbyte(a1, a0, 2);                  \
+        const uint32_t n0 = a0 << 16;                                               \
+        a0 = xor3(xor3(n0, ra, rb), m1.x, m0.x);                                    \
+        a1 = xor3(n1, m1.y, m0.y);                                                  \
+        a2 = xor3(n2, m1.z, m0.z);                                                  \
+        a3 = xor3(n3, m1.w, m0.w);                                                  \
+    } while (0)
+    AESMI_WSTEP(6);
+    AESMI_WSTEP(5);
+    AESMI_WSTEP(4);
+    AESMI_WSTEP(3);
+    AESMI_WSTEP(2);
+    AESMI_WSTEP(1);
+    AESMI_WSTEP(0);
+#undef AESMI_WSTEP
+    y[0] = a0 ^ x[0];
+    y[1] = a1 ^ x[1];
+    y[2] = a2 ^ x[2];
+    y[3] = a3 ^ x[3];
+}
 
 // One copy of each table (4 KiB + 1 KiB) for narrow passes and the final wave.
 struct FlatLayout {
@@ -291,14 +351,25 @@ __device__ void load_partial(uint32_t (&x)[4], const uint8_t *p, uint64_t len)
 
 // A plain array of n 16-byte values.
 struct ArraySrc {
+    static constexpr bool kAllDirect = true;
     const u32x4 *v;
+
+    __device__ __forceinline__ const u32x4 *at(uint64_t u) const
+    {
+        return v + u;
+    }
+
+    __device__ __forceinline__ void load(uint32_t (&x)[4], uint64_t u) const
+    {
+        load4(x, v + u);
+    }
 
     __device__ __forceinline__ void fetch(uint32_t (&x)[4], int64_t r) const
     {
         if (r < 0)
             zero4(x);
         else
-            load4(x, v + r);
+            load(x, (uint64_t)r);
     }
 };
 
@@ -312,11 +383,22 @@ struct GcmSrc {
 
     __device__ void fetch(uint32_t (&x)[4], int64_t r) const
     {
-        if (r < 0) {
+        if (r < 0)
             zero4(x);
-            return;
-        }
-        const uint64_t u = (uint64_t)r;
+        else
+            load(x, (uint64_t)r);
+    }
+
+    static constexpr bool kAllDirect = false;
+
+    // Whole ciphertext blocks, u in [na, na + nc_full), load directly.
+    __device__ __forceinline__ const u32x4 *at(uint64_t u) const
+    {
+        return reinterpret_cast<const u32x4 *>(c) + (u - na);
+    }
+
+    __device__ void load(uint32_t (&x)[4], uint64_t u) const
+    {
         if (u >= na && u - na < nc_full) {
             load4(x, c + 16 * (u - na));
         } else if (u < na_full) {
@@ -381,31 +463,66 @@ __global__ __launch_bounds__(64) void ghash_setup_kernel(uint32_t h0, uint32_t h
 }
 
 // One pass: T = gridDim * blockDim * CH virtual lanes, J blocks each, front
-// padding pad, multiplier H^T = pow[e]; writes Y_0..Y_(T-1).
+// padding pad < T (so only the first block of a lane can be padding),
+// multiplier H^T = pow[e]; writes Y_0..Y_(T-1).
 template <class Src, int CH>
-__global__ __launch_bounds__(1024) void ghash_pass_main_kernel(Src src, uint64_t pad, uint64_t T,
+__global__ __launch_bounds__(1024) void ghash_pass_wide_kernel(Src src, uint64_t pad, uint64_t T,
                                                                uint64_t J,
                                                                const GcmHdr *__restrict__ hdr,
                                                                uint32_t e, u32x4 *__restrict__ out)
 {
-    __shared__ __attribute__((aligned(16))) char lds[MainLayout::kLds];
-    MainLayout::fill(lds, hdr->pow[e]);
+    __shared__ __attribute__((aligned(16))) char lds[WideLayout::kLds];
+    WideLayout::fill(lds, hdr->pow[e]);
     __syncthreads();
-    const MainLayout lay(threadIdx.x);
+    const WideLayout lay(threadIdx.x);
     const uint64_t nthr = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t y[CH][4];
 #pragma unroll
     for (int i = 0; i < CH; ++i)
         src.fetch(y[i], (int64_t)(gid + i * nthr) - (int64_t)pad);
-    for (uint64_t j = 1; j < J; ++j) {
-        uint32_t x[CH][4];
+    // Steps [jlo, jhi) read whole ciphertext blocks in every chain of the
+    // wave (the wave's 64 lanes take 64 consecutive blocks); they run a loop
+    // with plain loads, the few steps outside it the general loader.
+    uint64_t jlo = 1, jhi = J;
+    if constexpr (!Src::kAllDirect) {
+        const int64_t wb = __builtin_amdgcn_readfirstlane((uint32_t)gid);
+        const int64_t lo = (int64_t)src.na, hi = (int64_t)(src.na + src.nc_full) - 64;
+        int64_t a = 1, b = (int64_t)J;
 #pragma unroll
-        for (int i = 0; i < CH; ++i)
-            src.fetch(x[i], (int64_t)(gid + i * nthr + j * T) - (int64_t)pad);
+        for (int i = 0; i < CH; ++i) {
+            const int64_t u0 = wb + i * (int64_t)nthr - (int64_t)pad;
+            const int64_t ja = lo > u0 ? (lo - u0 + (int64_t)T - 1) / (int64_t)T : 0;
+            const int64_t jb = hi >= u0 ? (hi - u0) / (int64_t)T + 1 : 0;
+            a = ja > a ? ja : a;
+            b = jb < b ? jb : b;
+        }
+        jlo = (uint64_t)a;
+        jhi = (uint64_t)(b > a ? b : a);
+    }
+    for (uint64_t j = 1; j < J;) {
+        if (j >= jlo && j < jhi) {
+            for (; j < jhi; ++j) {
+                uint32_t x[CH][4];
 #pragma unroll
-        for (int i = 0; i < CH; ++i)
-            gmul_acc(y[i], x[i], lds, lay);
+                for (int i = 0; i < CH; ++i)
+                    load4(x[i], src.at(gid + i * nthr + j * T - pad));
+#pragma unroll
+                for (int i = 0; i < CH; ++i)
+                    gmul_wide(y[i], x[i], lds, lay);
+            }
+        } else {
+            const uint64_t end = j < jlo ? (jlo < J ? jlo : J) : J;
+            for (; j < end; ++j) {
+                uint32_t x[CH][4];
+#pragma unroll
+                for (int i = 0; i < CH; ++i)
+                    src.load(x[i], gid + i * nthr + j * T - pad);
+#pragma unroll
+                for (int i = 0; i < CH; ++i)
+                    gmul_wide(y[i], x[i], lds, lay);
+            }
+        }
     }
 #pragma unroll
     for (int i = 0; i < CH; ++i)
@@ -428,7 +545,7 @@ __global__ __launch_bounds__(256) void ghash_pass_flat_kernel(Src src, uint64_t 
     src.fetch(y, (int64_t)gid - (int64_t)pad);
     for (uint64_t j = 1; j < J; ++j) {
         uint32_t x[4];
-        src.fetch(x, (int64_t)(gid + j * T) - (int64_t)pad);
+        src.load(x, gid + j * T - pad);
         gmul_acc(y, x, lds, lay);
     }
     out[gid] = u32x4{y[0], y[1], y[2], y[3]};
@@ -530,15 +647,15 @@ hipError_t run_passes(const Plan &p, const Src &src0, char *ws, uint64_t n0, voi
         const uint64_t T = p.T[l], J = p.J[l], pad = T * J - p.n[l];
         const uint32_t e = log2u(T);
         u32x4 *out = buf[l & 1];
-        if (T >= kMainMinT) {
+        if (T >= kWideMinT) {
             constexpr int kCh = 2;
             const uint32_t wg = 1024;
             const uint32_t grid = (uint32_t)(T / (kCh * wg));
             if (l == 0)
-                hipLaunchKernelGGL((ghash_pass_main_kernel<Src, kCh>), dim3(grid), dim3(wg), 0,
+                hipLaunchKernelGGL((ghash_pass_wide_kernel<Src, kCh>), dim3(grid), dim3(wg), 0,
                                    stream, src0, pad, T, J, hdr, e, out);
             else
-                hipLaunchKernelGGL((ghash_pass_main_kernel<ArraySrc, kCh>), dim3(grid), dim3(wg),
+                hipLaunchKernelGGL((ghash_pass_wide_kernel<ArraySrc, kCh>), dim3(grid), dim3(wg),
                                    0, stream, ArraySrc{buf[(l - 1) & 1]}, pad, T, J, hdr, e, out);
         } else {
             const uint32_t wg = (uint32_t)(T < 256 ? T : 256);
