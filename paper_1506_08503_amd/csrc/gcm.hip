@@ -19,9 +19,9 @@
 // lookups per step (about 110 VALU ops and 16 + 14 LDS reads per block).
 // The tables live in LDS, replicated so that lanes never share a bank, each
 // address one v_perm_b32 of a data word with a per-lane constant:
-//   M, M'  256 entries x 8 copies x 16 B, interleaved (b << 8 | t << 7 | c << 4)
-//   R      256 entries x 64 copies x 4 B at 0x10000 (o << 8 | lane << 2)
-// 128 KiB per workgroup.  Narrow passes and the final wave use one copy of a
+//   M, M'  256 entries x 16 copies x 16 B each (t << 16 | b << 8 | c << 4)
+//   R      256 entries x 32 copies x 4 B at 0x20000 (o << 7 | lane << 2)
+// 160 KiB per workgroup.  Narrow passes and the final wave use one copy of a
 // one-byte-step table.
 //
 // Parallel GHASH.  Pad the sequence with zeros in front to T * J blocks (a
@@ -143,17 +143,21 @@ __device__ __forceinline__ uint32_t reduce_entry(uint32_t o)
 }
 
 // ------------------------------------------------------------ table layouts
-// Replicated, bank-conflict-free layout for wide passes (128 KiB), two bytes
-// per Horner step: M0[b] = b(x) G and M1[b] = b(x) x^8 G interleaved, 8
-// copies of 16 bytes each (entry b, table t, copy c at b << 8 | t << 7 |
-// c << 4: eight consecutive lanes read eight distinct 16-byte bank groups),
-// then R with 64 copies of one word at 0x10000 | o << 8 | lane << 2.
+// Replicated, bank-conflict-free layout for wide passes (160 KiB, the whole
+// LDS of a CU), two bytes per Horner step.  M0[b] = b(x) G and M1[b] =
+// b(x) x^8 G, 16 copies of 16 bytes each (table t, entry b, copy c at
+// t << 16 | b << 8 | c << 4): ds_read_b128 serves 16 lanes per pass, and
+// lanes 0-15 of every pass read 16 distinct 16-byte bank groups.  R with 32
+// copies of one word at 0x20000 | o << 7 | (lane & 31) << 2 (32 lanes per
+// pass for ds_read_b32).  M addresses are one v_perm_b32, R addresses a shift
+// and an and-or.
 struct WideLayout {
-    static constexpr uint32_t kLds = 0x20000u;
+    static constexpr uint32_t kLds = 0x28000u;
     uint32_t c0, c1, cr;
 
     __device__ explicit WideLayout(uint32_t tid)
-        : c0((tid & 7u) << 4), c1(0x80u | ((tid & 7u) << 4)), cr(0x10000u | ((tid & 63u) << 2))
+        : c0((tid & 15u) << 4), c1(0x10000u | ((tid & 15u) << 4)),
+          cr(0x20000u | ((tid & 31u) << 2))
     {
     }
 
@@ -165,11 +169,11 @@ struct WideLayout {
         return *reinterpret_cast<const u32x4 *>(lds + a);
     }
 
-    // R[byte K of w]
+    // R[byte K of w], K >= 1
     template <int K>
     __device__ __forceinline__ uint32_t r(const char *lds, uint32_t w) const
     {
-        const uint32_t a = __builtin_amdgcn_perm(w, cr, 0x0c020000u | ((4u + K) << 8));
+        const uint32_t a = ((w >> (8 * K - 7)) & 0x7F80u) | cr;
         return *reinterpret_cast<const uint32_t *>(lds + a);
     }
 
@@ -179,14 +183,14 @@ struct WideLayout {
         basis8(g, b0);
         V4 g8 = mul_x(b0[7]);
         basis8(u32x4{g8.w[0], g8.w[1], g8.w[2], g8.w[3]}, b1);
-        for (uint32_t e = threadIdx.x; e < 256u * 2u * 8u; e += blockDim.x) {
-            const uint32_t idx = e >> 4, t = (e >> 3) & 1u, c = e & 7u;
-            *reinterpret_cast<u32x4 *>(lds + (idx << 8) + (t << 7) + (c << 4)) =
+        for (uint32_t e = threadIdx.x; e < 2u * 256u * 16u; e += blockDim.x) {
+            const uint32_t t = e >> 12, idx = (e >> 4) & 255u, c = e & 15u;
+            *reinterpret_cast<u32x4 *>(lds + (t << 16) + (idx << 8) + (c << 4)) =
                 t ? table_entry(b1, idx) : table_entry(b0, idx);
         }
-        for (uint32_t e = threadIdx.x; e < 256u * 64u; e += blockDim.x) {
-            const uint32_t o = e >> 6, l = e & 63u;
-            *reinterpret_cast<uint32_t *>(lds + 0x10000u + (o << 8) + (l << 2)) = reduce_entry(o);
+        for (uint32_t e = threadIdx.x; e < 256u * 32u; e += blockDim.x) {
+            const uint32_t o = e >> 5, l = e & 31u;
+            *reinterpret_cast<uint32_t *>(lds + 0x20000u + (o << 7) + (l << 2)) = reduce_entry(o);
         }
     }
 };

@@ -6,6 +6,8 @@ tails; the 4 GiB stream is checked on a sample of blocks the oracle computes
 one by one (CTR allows random access), in the launch configuration the
 benchmark times.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -278,3 +280,28 @@ def test_stream_4gib_sampled(oracle):
     x2 = x.clone()
     am.ctr_xcrypt(ks, inp.nonce, inp.ctr0, x2, out=x2)
     assert torch.equal(x2, y)
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(os.environ.get("AESMI_FULL_COMPARE") != "1",
+                    reason="every byte of 4 GiB against the threaded oracle takes minutes of "
+                           "host CPU; run with AESMI_FULL_COMPARE=1")
+def test_stream_4gib_full_oracle(oracle):
+    """Every byte of the 4 GiB AES-128 CTR output against the oracle, which
+    recomputes the stream in 64 MiB pieces on all host threads."""
+    inp = wl.stream_4g_inputs()
+    x = fill_device(inp)
+    ks = am.key_schedule(inp.key)
+    y = am.ctr_xcrypt(ks, inp.nonce, inp.ctr0, x)
+    torch.cuda.synchronize()
+    threads = min(16, os.cpu_count() or 1)
+    piece = 64 << 20
+    for off, chunk in inp.plaintext_chunks():
+        for lo in range(0, chunk.size, piece):
+            part = chunk[lo:lo + piece]
+            start = off + lo
+            exp = oracle.ctr_xcrypt(inp.key, inp.nonce, inp.ctr0 + start // 16, part,
+                                    threads=threads)
+            got = y[start:start + part.size].cpu().numpy()
+            assert np.array_equal(got, exp), start
+        print("full compare: %d MiB equal" % ((off + chunk.size) >> 20), flush=True)
