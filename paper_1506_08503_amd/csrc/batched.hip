@@ -9,7 +9,9 @@
 //   1. prepare (one workgroup): validates every segment, counts its tiles,
 //      writes the exclusive prefix sums tile_start[0..nsegs] and clears the
 //      tile counter and the status word in the workspace.  Invalid segments
-//      get no tiles and set the status word to AES_ERR_SEGMENT.
+//      get no tiles and set the status word to AES_ERR_SEGMENT (a key
+//      schedule without a valid round count is caught by the CTR kernel,
+//      which skips the segment's tiles and sets the same status).
 //   2. persistent CTR kernel (a fixed grid of workgroups per CU): each wave
 //      claims tile t with one atomic add, finds its segment with a 64-way
 //      ballot search over tile_start (three rounds for 10^4 segments), loads
@@ -42,16 +44,14 @@ __device__ __forceinline__ uint32_t *tile_start_of(void *ws)
 }
 
 // Tiles of one segment, or 0 when it is empty or invalid (then *bad is set).
-__device__ uint32_t segment_tiles(const aes_segment_t &sg, const aes_key_schedule_t *ks_table,
-                                  uint32_t nkeys, uint32_t tile_blocks, bool *bad)
+// The round count of its key schedule is checked by the CTR kernels, which
+// skip such a segment's tiles and set the status word.
+__device__ __forceinline__ uint32_t segment_tiles(const aes_segment_t &sg, uint32_t nkeys,
+                                                  uint32_t tile_blocks, bool *bad)
 {
     const uint64_t nblk = (sg.nbytes + 15u) >> 4;
-    bool ok = sg.key_slot < nkeys && sg.reserved == 0 && (sg.in_off & 15u) == 0 &&
-              (sg.out_off & 15u) == 0 && (uint64_t)sg.ctr0 + nblk <= (1ull << 32);
-    if (ok && nblk) {
-        const uint32_t nr = ks_table[sg.key_slot].nr;
-        ok = nr == 10 || nr == 12 || nr == 14;
-    }
+    const bool ok = sg.key_slot < nkeys && sg.reserved == 0 && (sg.in_off & 15u) == 0 &&
+                    (sg.out_off & 15u) == 0 && (uint64_t)sg.ctr0 + nblk <= (1ull << 32);
     if (!ok) {
         *bad = true;
         return 0;
@@ -59,6 +59,13 @@ __device__ uint32_t segment_tiles(const aes_segment_t &sg, const aes_key_schedul
     return (uint32_t)((nblk + tile_blocks - 1) / tile_blocks);
 }
 
+constexpr uint32_t kPrepLdsSegs = 12288;   // tile counts kept in LDS up to this many segments
+constexpr int kPrepInFlight = 8;           // segments loaded at once per thread
+
+// One workgroup.  Pass 1 reads the table coalesced (segment s by thread
+// s mod blockDim, several segments in flight) and stores each segment's tile
+// count (it does not read the key schedules); pass 2 turns contiguous runs of counts into exclusive prefix sums
+// with a scan of the per-thread run totals.
 __global__ __launch_bounds__(1024) void batched_prepare(const aes_segment_t *__restrict__ segs,
                                                         uint32_t nsegs,
                                                         const aes_key_schedule_t *__restrict__ ks_table,
@@ -66,23 +73,42 @@ __global__ __launch_bounds__(1024) void batched_prepare(const aes_segment_t *__r
                                                         uint32_t tile_blocks)
 {
     __shared__ uint32_t part[1024];
+    __shared__ uint32_t cnt_lds[kPrepLdsSegs];
     __shared__ int bad_any;
     WsHeader *h = static_cast<WsHeader *>(ws);
     uint32_t *start = tile_start_of(ws);
+    uint32_t *cnt = nsegs <= kPrepLdsSegs ? cnt_lds : start;
     const uint32_t nt = blockDim.x, tid = threadIdx.x;
     if (tid == 0)
         bad_any = 0;
-    // contiguous chunk of segments per thread
-    const uint32_t per = (nsegs + nt - 1) / nt;
-    const uint32_t lo = min(nsegs, tid * per), hi = min(nsegs, lo + per);
-    bool bad = false;
-    uint32_t sum = 0;
-    for (uint32_t s = lo; s < hi; ++s)
-        sum += segment_tiles(segs[s], ks_table, nkeys, tile_blocks, &bad);
-    part[tid] = sum;
     __syncthreads();
+    bool bad = false;
+    for (uint32_t s0 = tid; s0 < nsegs; s0 += kPrepInFlight * nt) {
+        aes_segment_t sg[kPrepInFlight];
+#pragma unroll
+        for (int k = 0; k < kPrepInFlight; ++k) {
+            const uint32_t s = s0 + k * nt;
+            if (s < nsegs)
+                sg[k] = segs[s];
+        }
+#pragma unroll
+        for (int k = 0; k < kPrepInFlight; ++k) {
+            const uint32_t s = s0 + k * nt;
+            if (s < nsegs)
+                cnt[s] = segment_tiles(sg[k], nkeys, tile_blocks, &bad);
+        }
+    }
     if (bad)
         bad_any = 1;
+    __syncthreads();
+    const uint32_t per = (nsegs + nt - 1) / nt;
+    const uint32_t lo = min(nsegs, tid * per), hi = min(nsegs, lo + per);
+    uint32_t sum = 0;
+#pragma unroll 8
+    for (uint32_t s = lo; s < hi; ++s)
+        sum += cnt[s];
+    part[tid] = sum;
+    __syncthreads();
     // inclusive scan of the per-thread sums (Hillis-Steele in LDS)
     for (uint32_t off = 1; off < nt; off <<= 1) {
         uint32_t v = tid >= off ? part[tid - off] : 0u;
@@ -90,11 +116,12 @@ __global__ __launch_bounds__(1024) void batched_prepare(const aes_segment_t *__r
         part[tid] += v;
         __syncthreads();
     }
-    uint32_t run = part[tid] - sum;   // exclusive prefix of this chunk
+    uint32_t run = part[tid] - sum;   // exclusive prefix of this run
+#pragma unroll 8
     for (uint32_t s = lo; s < hi; ++s) {
-        bool b2 = false;
+        const uint32_t c = cnt[s];
         start[s] = run;
-        run += segment_tiles(segs[s], ks_table, nkeys, tile_blocks, &b2);
+        run += c;
     }
     __syncthreads();
     if (tid == nt - 1) {
@@ -119,7 +146,9 @@ __device__ __forceinline__ uint32_t find_segment(const uint32_t *__restrict__ st
         const uint32_t idx = lo + lane * step;
         const bool ok = idx < hi && start[idx] <= t;
         const uint64_t m = __ballot(ok);
-        const uint32_t last = 63u - (uint32_t)__clzll((long long)m);
+        // lane 0 tests start[lo] <= t, which always holds: m is never 0 on a
+        // full wave (the guard keeps lo in range regardless)
+        const uint32_t last = m ? 63u - (uint32_t)__clzll((long long)m) : 0u;
         lo += last * step;
         hi = min(lo + step, hi);
     }
@@ -132,6 +161,16 @@ __device__ __forceinline__ uint32_t claim_tile(WsHeader *h, uint32_t lane)
     if (lane == 0)
         t = atomicAdd(&h->counter, 1u);
     return __builtin_amdgcn_readfirstlane(t);
+}
+
+// A segment whose key schedule has no valid round count: its tiles are
+// skipped (the output stays untouched) and the status word says so.  Every
+// lane stores the same word: a lane-divergent store here let the compiler
+// split the claim loop into per-lane iterations, and the claim and the
+// segment search need the whole wave.
+__device__ __forceinline__ void report_bad_schedule(WsHeader *h)
+{
+    h->status = (int32_t)AES_ERR_SEGMENT;
 }
 
 struct TileJob {
@@ -231,7 +270,7 @@ __global__ __launch_bounds__(1024) void batched_ttable_kernel(
         case 10: ttable_tile<10>(j, lds, lc, lane); break;
         case 12: ttable_tile<12>(j, lds, lc, lane); break;
         case 14: ttable_tile<14>(j, lds, lc, lane); break;
-        default: break;
+        default: report_bad_schedule(h); break;
         }
     }
 }
@@ -264,7 +303,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         case 10: bitslice_tile<10>(j); break;
         case 12: bitslice_tile<12>(j); break;
         case 14: bitslice_tile<14>(j); break;
-        default: break;
+        default: report_bad_schedule(h); break;
         }
     }
 }

@@ -22,6 +22,18 @@ __constant__ uint8_t g_sbox[256] = {
 #undef X
 };
 
+template <uint32_t NK>
+__device__ __forceinline__ void expand_one(const uint8_t *__restrict__ keys, uint64_t k,
+                                           aes_key_schedule_t *__restrict__ out,
+                                           const uint8_t *sbox)
+{
+    uint8_t key[4 * NK];
+#pragma unroll
+    for (uint32_t i = 0; i < 4 * NK; ++i)
+        key[i] = keys[k * (4 * NK) + i];
+    expand_schedule_nk<NK>(key, out + k, sbox);
+}
+
 __global__ __launch_bounds__(256) void expand_keys_kernel(const uint8_t *__restrict__ keys,
                                                           uint32_t key_bytes, uint64_t nkeys,
                                                           aes_key_schedule_t *__restrict__ out)
@@ -33,12 +45,12 @@ __global__ __launch_bounds__(256) void expand_keys_kernel(const uint8_t *__restr
     const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nkeys)
         return;
-    uint8_t key[32];
-    for (uint32_t i = 0; i < key_bytes; ++i)
-        key[i] = keys[k * key_bytes + i];
-    aes_key_schedule_t ks;
-    expand_schedule(key, key_bytes, &ks, sbox);
-    out[k] = ks;
+    if (key_bytes == 16)
+        expand_one<4>(keys, k, out, sbox);
+    else if (key_bytes == 24)
+        expand_one<6>(keys, k, out, sbox);
+    else
+        expand_one<8>(keys, k, out, sbox);
 }
 
 }  // namespace

@@ -19,21 +19,15 @@
 
 namespace aesmi {
 
-__host__ __device__ inline uint8_t ks_xtime(uint8_t a)
+// x * w in GF(2^8) for the four bytes of w at once (reduction by 0x11B).
+__host__ __device__ inline uint32_t ks_xtime4(uint32_t w)
 {
-    return static_cast<uint8_t>((a << 1) ^ ((a & 0x80) ? 0x1B : 0x00));
+    return ((w & 0x7f7f7f7fu) << 1) ^ (((w >> 7) & 0x01010101u) * 0x1bu);
 }
 
-__host__ __device__ inline uint8_t ks_mul(uint8_t a, uint8_t b)
+__host__ __device__ inline uint32_t ks_rotr8(uint32_t w, unsigned s)
 {
-    uint8_t acc = 0;
-    while (b) {
-        if (b & 1)
-            acc ^= a;
-        a = ks_xtime(a);
-        b >>= 1;
-    }
-    return acc;
+    return (w >> s) | (w << (32u - s));
 }
 
 __host__ __device__ inline uint32_t ks_subword(uint32_t w, const uint8_t *sbox)
@@ -44,55 +38,72 @@ __host__ __device__ inline uint32_t ks_subword(uint32_t w, const uint8_t *sbox)
            (static_cast<uint32_t>(sbox[w >> 24]) << 24);
 }
 
+// InvMixColumns of one column word: byte i of the result is
+// 14 a_i ^ 11 a_(i+1) ^ 13 a_(i+2) ^ 9 a_(i+3) (mix row [14 11 13 9], App. A4);
+// the multiples come from the chain a -> 2a -> 4a -> 8a.
 __host__ __device__ inline uint32_t ks_inv_mix(uint32_t w)
 {
-    uint8_t a[4] = {static_cast<uint8_t>(w), static_cast<uint8_t>(w >> 8),
-                    static_cast<uint8_t>(w >> 16), static_cast<uint8_t>(w >> 24)};
-    uint32_t out = 0;
-    for (int i = 0; i < 4; ++i) {
-        uint8_t v = ks_mul(14, a[i]) ^ ks_mul(11, a[(i + 1) & 3]) ^
-                    ks_mul(13, a[(i + 2) & 3]) ^ ks_mul(9, a[(i + 3) & 3]);
-        out |= static_cast<uint32_t>(v) << (8 * i);
+    const uint32_t w2 = ks_xtime4(w), w4 = ks_xtime4(w2), w8 = ks_xtime4(w4);
+    const uint32_t w9 = w8 ^ w, w11 = w9 ^ w2, w13 = w9 ^ w4, w14 = w8 ^ w4 ^ w2;
+    return w14 ^ ks_rotr8(w11, 8) ^ ks_rotr8(w13, 16) ^ ks_rotr8(w9, 24);
+}
+
+// The schedule for Nk = NK key words; every index is a compile-time constant
+// so the words stay in registers on the device.
+template <uint32_t NK>
+__host__ __device__ inline void expand_schedule_nk(const uint8_t *key, aes_key_schedule_t *ks,
+                                                   const uint8_t *sbox)
+{
+    constexpr uint32_t nr = NK + 6;
+    constexpr uint32_t nw = 4 * (nr + 1);
+    uint32_t w[nw];
+#pragma unroll
+    for (uint32_t i = 0; i < NK; ++i)
+        w[i] = static_cast<uint32_t>(key[4 * i]) | (static_cast<uint32_t>(key[4 * i + 1]) << 8) |
+               (static_cast<uint32_t>(key[4 * i + 2]) << 16) |
+               (static_cast<uint32_t>(key[4 * i + 3]) << 24);
+    uint32_t rcon = 1;
+#pragma unroll
+    for (uint32_t i = NK; i < nw; ++i) {
+        uint32_t t = w[i - 1];
+        if (i % NK == 0) {
+            t = ks_subword((t >> 8) | (t << 24), sbox) ^ rcon;
+            rcon = ks_xtime4(rcon) & 0xffu;
+        } else if (NK == 8 && i % NK == 4) {
+            t = ks_subword(t, sbox);
+        }
+        w[i] = w[i - NK] ^ t;
     }
-    return out;
+    ks->nr = nr;
+    ks->key_bytes = 4 * NK;
+#pragma unroll
+    for (uint32_t i = 0; i < 60; ++i)
+        ks->rk_enc[i] = i < nw ? w[i] : 0u;
+#pragma unroll
+    for (uint32_t c = 0; c < 4; ++c) {
+        ks->rk_dec[c] = w[4 * nr + c];
+        ks->rk_dec[4 * nr + c] = w[c];
+    }
+#pragma unroll
+    for (uint32_t r = 1; r < nr; ++r)
+#pragma unroll
+        for (uint32_t c = 0; c < 4; ++c)
+            ks->rk_dec[4 * r + c] = ks_inv_mix(w[4 * (nr - r) + c]);
+#pragma unroll
+    for (uint32_t i = 4 * (nr + 1); i < 60; ++i)
+        ks->rk_dec[i] = 0u;
 }
 
 // key_bytes must be 16, 24 or 32 (checked by the caller).
 __host__ __device__ inline void expand_schedule(const uint8_t *key, uint32_t key_bytes,
                                                 aes_key_schedule_t *ks, const uint8_t *sbox)
 {
-    const uint32_t nk = key_bytes / 4;
-    const uint32_t nr = nk + 6;
-    const uint32_t nw = 4 * (nr + 1);
-    uint32_t w[60];
-    for (uint32_t i = 0; i < nk; ++i)
-        w[i] = static_cast<uint32_t>(key[4 * i]) | (static_cast<uint32_t>(key[4 * i + 1]) << 8) |
-               (static_cast<uint32_t>(key[4 * i + 2]) << 16) |
-               (static_cast<uint32_t>(key[4 * i + 3]) << 24);
-    uint8_t rcon = 1;
-    for (uint32_t i = nk; i < nw; ++i) {
-        uint32_t t = w[i - 1];
-        if (i % nk == 0) {
-            t = ks_subword((t >> 8) | (t << 24), sbox) ^ rcon;
-            rcon = ks_xtime(rcon);
-        } else if (nk == 8 && i % nk == 4) {
-            t = ks_subword(t, sbox);
-        }
-        w[i] = w[i - nk] ^ t;
-    }
-    ks->nr = nr;
-    ks->key_bytes = key_bytes;
-    for (uint32_t i = 0; i < 60; ++i) {
-        ks->rk_enc[i] = i < nw ? w[i] : 0u;
-        ks->rk_dec[i] = 0u;
-    }
-    for (uint32_t c = 0; c < 4; ++c) {
-        ks->rk_dec[c] = w[4 * nr + c];
-        ks->rk_dec[4 * nr + c] = w[c];
-    }
-    for (uint32_t r = 1; r < nr; ++r)
-        for (uint32_t c = 0; c < 4; ++c)
-            ks->rk_dec[4 * r + c] = ks_inv_mix(w[4 * (nr - r) + c]);
+    if (key_bytes == 16)
+        expand_schedule_nk<4>(key, ks, sbox);
+    else if (key_bytes == 24)
+        expand_schedule_nk<6>(key, ks, sbox);
+    else
+        expand_schedule_nk<8>(key, ks, sbox);
 }
 
 }  // namespace aesmi

@@ -150,6 +150,37 @@ def test_batched_invalid_segments(oracle):
             assert np.array_equal(o[a:a + ln], exp), i
 
 
+@pytest.mark.parametrize("tune", [None, TUNES[4]], ids=["ttable", "bitslice"])
+def test_batched_invalid_key_schedule(oracle, tune):
+    """A key slot whose schedule has no valid round count: its segments are
+    left untouched and the status says AES_ERR_SEGMENT; the others are right."""
+    g = _rng(10)
+    n = 6
+    lengths = np.array([16 * 4096 + 5, 100, 16 * 5000, 33, 16 * 2048, 7], np.int64)
+    in_off, total = wl.pack_offsets(lengths)
+    keys = [g.bytes(16) for _ in range(3)]
+    nonces = np.frombuffer(g.bytes(12 * n), np.uint8).reshape(n, 12)
+    slots = np.array([0, 1, 2, 1, 0, 2], np.uint32)
+    segs_h = bt.segment_table(in_off, in_off, lengths, slots, np.zeros(n, np.uint32), nonces)
+    pt = np.frombuffer(g.bytes(total + 16), np.uint8).copy()
+    x = torch.from_numpy(pt).to(DEV)
+    out = torch.full_like(x, 0x5A)
+    table = key_table(keys)
+    table[1, 0:4] = torch.tensor([9, 0, 0, 0], dtype=torch.uint8)   # nr = 9
+    ws = bt.workspace(n, DEV)
+    am.ctr_xcrypt_batched(torch.from_numpy(segs_h.view(np.uint8).copy()).to(DEV), table, x,
+                          out, ws, tune)
+    assert am.batched_read_status(ws) == -7
+    o = out.cpu().numpy()
+    for i in range(n):
+        a, ln = int(in_off[i]), int(lengths[i])
+        if slots[i] == 1:
+            assert np.all(o[a:a + ln] == 0x5A), i
+        else:
+            exp = oracle.ctr_xcrypt(keys[slots[i]], nonces[i].tobytes(), 0, pt[a:a + ln])
+            assert np.array_equal(o[a:a + ln], exp), i
+
+
 def test_batched_graph_replays(mixed):
     """A captured graph replayed three times, the input rewritten in place with
     eager work and synchronizations in between; every replay equals an eager
