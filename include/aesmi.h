@@ -5,7 +5,10 @@
  * AES cipher (key expansion; rounds of SubBytes, ShiftRows, MixColumns and
  * AddRoundKey, the last round without MixColumns) in ECB and counter (CTR)
  * mode, as framed algebraically in Kepner et al., arXiv 1506.08503 (sec. II,
- * App. A1-A5).  128-, 192- and 256-bit keys (10, 12, 14 rounds).
+ * App. A1-A5).  128-, 192- and 256-bit keys (10, 12, 14 rounds).  Also: the
+ * paper's CBC over a matrix of messages (App. A1, A4), many messages with
+ * their own keys in one launch (the per-row V and K of sec. II), and GCM
+ * (NIST SP 800-38D) for authenticated encryption.
  *
  * Conventions shared by every entry point
  *  - Plain C types only.  Device buffers are raw device pointers; `stream` is

@@ -2,8 +2,9 @@
 
 Kepner et al., "Parallel Vectorized Algebraic AES in MATLAB ..." (arXiv
 1506.08503) frames AES as GF(2^8) algebra vectorized over many messages; this
-package runs that cipher (ECB and CTR, 128/192/256-bit keys) as hand-written
-HIP kernels behind the C ABI in ``include/aesmi.h``.  ``aesmi`` is the thin
+package runs that cipher (ECB and CTR, the paper's CBC over a message matrix,
+and GCM; 128/192/256-bit keys) as hand-written HIP kernels behind the C ABI in
+``include/aesmi.h``.  ``aesmi`` is the thin
 Python binding; ``batch`` and ``serve`` add many-message batching and a
 continuous-batching request loop on top.
 """
