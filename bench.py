@@ -315,9 +315,9 @@ def main():
     alg_bytes = 32 * nblocks
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     kernel_name = {("ctr", False): "ctr_grouped_kernel", ("ctr", True): "ctr_bitslice_kernel",
-                   ("ecb-enc", False): "ecb_ttable_kernel<false, 4>",
+                   ("ecb-enc", False): "ecb_ttable_kernel<false, 0>",
                    ("ecb-enc", True): "ecb_bitslice_kernel<false>",
-                   ("ecb-dec", False): "ecb_ttable_kernel<true, 4>",
+                   ("ecb-dec", False): "ecb_ttable_kernel<true, 0>",
                    ("ecb-dec", True): "ecb_bitslice_kernel<true>",
                    ("gcm-enc", False): "gcm step (ctr_grouped_kernel + ghash passes)",
                    ("gcm-dec", False): "gcm step (ghash passes + ctr_grouped_kernel)"}[
