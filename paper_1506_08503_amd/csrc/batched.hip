@@ -67,9 +67,7 @@ constexpr int kPrepInFlight = 8;           // segments loaded at once per thread
 // count (it does not read the key schedules); pass 2 turns contiguous runs of counts into exclusive prefix sums
 // with a scan of the per-thread run totals.
 __global__ __launch_bounds__(1024) void batched_prepare(const aes_segment_t *__restrict__ segs,
-                                                        uint32_t nsegs,
-                                                        const aes_key_schedule_t *__restrict__ ks_table,
-                                                        uint32_t nkeys, void *ws,
+                                                        uint32_t nsegs, uint32_t nkeys, void *ws,
                                                         uint32_t tile_blocks)
 {
     __shared__ uint32_t part[1024];
@@ -335,8 +333,8 @@ hipError_t batched_ctr(const aes_segment_t *segs, uint32_t nsegs,
     if (tile % 64u)
         return hipErrorInvalidConfiguration;
     const int cu = device_cu_count() > 0 ? device_cu_count() : 256;
-    hipLaunchKernelGGL(batched_prepare, dim3(1), dim3(1024), 0, stream, segs, nsegs, ks_table,
-                       nkeys, ws, tile);
+    hipLaunchKernelGGL(batched_prepare, dim3(1), dim3(1024), 0, stream, segs, nsegs, nkeys, ws,
+                       tile);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;

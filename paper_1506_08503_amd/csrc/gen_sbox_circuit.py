@@ -19,8 +19,17 @@ The AES field (polynomial 0x11B, sec. II) maps onto the tower by x -> beta,
 beta a root of x^8 + x^4 + x^3 + x + 1 in the tower; the map and the affine
 transform become 8 x 8 GF(2) matrices at the input and output.  Linear layers
 are built with greedy common-subexpression elimination (pairs shared by most
-outputs first).  Every (N, M, beta) choice is tried and the smallest circuit
-kept.  The affine constant 0x63 is NOT part of the circuit: it passes through
+outputs first).  Every (N, M, beta) choice is tried.
+
+gfx950 has a three-input logic op (v_bitop3_b32, any function of three
+words), so the gate graph is then covered by three-input operations: every
+gate gets its 3-feasible cuts (sets of at most three wires that separate it
+from the inputs), and an integer program picks the cuts that implement all
+outputs with the fewest operations (an operation needs every gate among its
+cut leaves to be implemented too).  The program runs (HiGHS through
+scipy.optimize.milp, with a node limit so that the result is reproducible) on
+the few circuits whose greedy single-fanout folding is smallest, and the
+smallest cover is kept.  The affine constant 0x63 is NOT part of the circuit: it passes through
 MixColumns unchanged (2 + 3 + 1 + 1 = 1 in GF(2^8)), so the kernels fold it into
 the round keys of rounds 1..Nr.
 
@@ -455,6 +464,79 @@ def fuse(c, outs):
     return fused
 
 
+def lut3_cover(c, outs, node_limit=2000):
+    """Cover the gate graph with three-input operations; returns the same
+    [(dst, leaves, expr)] list as fuse(), or None if no cover was found."""
+    import numpy as np
+    from scipy.optimize import Bounds, LinearConstraint, milp
+    from scipy.sparse import coo_matrix
+    gates = {dst: (op, a, b) for dst, op, a, b in c.gates}
+    order = [dst for dst, _, _, _ in c.gates]
+    cuts = {}
+
+    def with_trivial(w):
+        return cuts[w] + [frozenset([w])] if w in gates else [frozenset([w])]
+    for dst in order:
+        _, a, b = gates[dst]
+        found = {ca | cb for ca in with_trivial(a) for cb in with_trivial(b)
+                 if len(ca | cb) <= 3}
+        keep = []
+        for cut in sorted(found, key=lambda k: (len(k), sorted(k))):
+            if not any(k <= cut for k in keep):
+                keep.append(cut)
+        cuts[dst] = keep
+    var = [(dst, cut) for dst in order for cut in cuts[dst]]
+    index = {v: i for i, v in enumerate(var)}
+    rows, cols, vals, lo, hi = [], [], [], [], []
+
+    def constraint(coef, low, high):
+        for j, v in coef.items():
+            rows.append(len(lo))
+            cols.append(j)
+            vals.append(v)
+        lo.append(low)
+        hi.append(high)
+    for o in sorted(set(outs)):
+        if o in gates:
+            constraint({index[(o, cut)]: 1 for cut in cuts[o]}, 1, 1)
+    for dst in order:
+        constraint({index[(dst, cut)]: 1 for cut in cuts[dst]}, 0, 1)
+    for (dst, cut), i in index.items():
+        for leaf in sorted(cut):
+            if leaf in gates:
+                coef = {index[(leaf, k)]: 1 for k in cuts[leaf]}
+                coef[i] = coef.get(i, 0) - 1
+                constraint(coef, 0, np.inf)
+    a = coo_matrix((vals, (rows, cols)), shape=(len(lo), len(var))).tocsr()
+    res = milp(c=np.ones(len(var)), constraints=LinearConstraint(a, np.array(lo), np.array(hi)),
+               integrality=np.ones(len(var)), bounds=Bounds(0, 1),
+               options={"node_limit": node_limit, "disp": False})
+    if res.x is None:
+        return None
+    chosen = {var[i][0]: var[i][1] for i, v in enumerate(res.x) if v > 0.5}
+
+    def expr(w, cut):
+        if w in cut or w not in gates:
+            return w
+        op, x, y = gates[w]
+        return (op, expr(x, cut), expr(y, cut))
+
+    def leaves_of(e, acc):
+        if isinstance(e, str):
+            if e not in acc:
+                acc.append(e)
+        else:
+            leaves_of(e[1], acc)
+            leaves_of(e[2], acc)
+        return acc
+    out = []
+    for dst in order:
+        if dst in chosen:
+            e = expr(dst, chosen[dst])
+            out.append((dst, leaves_of(e, []), e))
+    return out
+
+
 def eval_expr(e, env):
     if isinstance(e, str):
         return env[e]
@@ -487,9 +569,12 @@ def evaluate(c, outs, x):
     return sum(val[o] << i for i, o in enumerate(outs))
 
 
-def search(target, inverse, trials=1):
+def search(target, inverse, trials=1, ilp_candidates=4):
+    """All (N, M, beta) towers (and `trials` randomized linear layers each);
+    the circuits with the smallest greedy folding are covered exactly and the
+    smallest result is returned."""
     import random
-    best = None
+    cands = []
     for n in (2, 3):                     # W, W^2 (trace 1 in GF(4))
         if trace(n, gf4_mul, 2) != 1:
             continue
@@ -509,31 +594,39 @@ def search(target, inverse, trials=1):
                     res = build(n, m, beta, inverse, rng)
                     if res is None:
                         break
-                    best = consider(best, res, target, n, m, beta)
+                    cands.append(check(res, target, n, m, beta))
+    cands.sort(key=lambda b: (b[0], b[7]))
+    best = cands[0]
+    for cand in cands[:ilp_candidates]:
+        c, outs = cand[8]
+        cover = lut3_cover(c, outs)
+        if cover is None:
+            continue
+        if any(evaluate_fused(cover, outs, x) != target[x] for x in range(256)):
+            raise SystemExit("three-input cover mismatch")
+        if len(cover) < best[0]:
+            best = (len(cover),) + cand[1:5] + (cover,) + cand[6:]
     return best
 
 
-def consider(best, res, target, n, m, beta):
-    """Check one candidate circuit on all 256 inputs (plain and fused) and keep
-    it if its fused op count is the lowest so far."""
+def check(res, target, n, m, beta):
+    """Check one candidate circuit on all 256 inputs (plain and greedily
+    folded) and return its record."""
     c, outs = res
     if any(evaluate(c, outs, x) != target[x] for x in range(256)):
         raise SystemExit("circuit mismatch for N=%d M=%d beta=%d" % (n, m, beta))
     fused = fuse(c, outs)
     if any(evaluate_fused(fused, outs, x) != target[x] for x in range(256)):
         raise SystemExit("fused circuit mismatch for N=%d M=%d beta=%d" % (n, m, beta))
-    nops = len(fused)
     nand = sum(1 for g in c.gates if g[1] == "&")
-    if best is None or (nops, len(c.gates)) < (best[0], best[7]):
-        best = (nops, nand, n, m, beta, fused, outs, len(c.gates))
-    return best
+    return (len(fused), nand, n, m, beta, fused, outs, len(c.gates), res)
 
 
 def emit(name, what, best):
-    nops, nand, n, m, beta, fused, outs, ngates = best
+    nops, nand, n, m, beta, fused, outs, ngates = best[:8]
     lines = ["// %s: tower field GF(((2^2)^2)^2), N=%d M=%d beta=0x%02x;"
              % (what, n, m, beta),
-             "// %d gates (%d AND) fused into %d VALU ops (two-input XOR/AND or one"
+             "// %d gates (%d AND) covered by %d VALU ops (two-input XOR/AND or one"
              % (ngates, nand, nops),
              "// three-input v_bitop3_b32 each).  Checked on all 256 inputs by the generator.",
              "#define %s(x0, x1, x2, x3, x4, x5, x6, x7, y0, y1, y2, y3, y4, y5, y6, y7) \\"
@@ -559,8 +652,9 @@ def main():
     for x, y in enumerate(sbox):
         inv_sbox[y] = x
     trials = int(os.environ.get("SBOX_SEARCH_TRIALS", "6"))
-    fwd = search([sbox[x] ^ 0x63 for x in range(256)], False, trials)
-    inv = search([inv_sbox[y ^ 0x63] for y in range(256)], True, trials)
+    ilp = int(os.environ.get("SBOX_ILP_CANDIDATES", "4"))
+    fwd = search([sbox[x] ^ 0x63 for x in range(256)], False, trials, ilp)
+    inv = search([inv_sbox[y ^ 0x63] for y in range(256)], True, trials, ilp)
     lines = ["// Generated by gen_sbox_circuit.py -- do not edit.",
              "// Bitsliced AES S-boxes with the affine constant 0x63 left out (the",
              "// kernels fold it into the round keys).  Inputs x0..x7 and outputs",
@@ -570,7 +664,7 @@ def main():
     with open(OUT, "w") as f:
         f.write("\n".join(lines) + "\n")
     for tag, b in (("forward", fwd), ("inverse", inv)):
-        print("%s: %d fused ops from %d gates (%d AND), N=%d M=%d beta=0x%02x"
+        print("%s: %d ops from %d gates (%d AND), N=%d M=%d beta=0x%02x"
               % (tag, b[0], b[7], b[1], b[2], b[3], b[4]))
 
 
