@@ -2,8 +2,9 @@
 style use the paper cites for equality queries over encrypted data, sec. I):
 2^26 int64 values, Zipf-distributed (s = 1.1) over 2^20 distinct values, each
 zero-padded to a 16-byte block.  Checks the round trip, that equal values give
-equal ciphertexts and distinct values distinct ones, and the oracle on a
-sample of rows."""
+equal ciphertexts and distinct values distinct ones, and every row against the
+oracle: ECB is deterministic, so the oracle enciphers each of the 2^20
+distinct values once and row i must equal the oracle block of its value."""
 import numpy as np
 import pytest
 import torch
@@ -54,3 +55,8 @@ def test_dbcolumn_aes256_ecb(oracle):
     assert np.array_equal(ct_s, oracle.ecb_encrypt(col.key, pt_s, threads=8))
     packed = wl.pack_int64_blocks(col.values[col.ranks[idx]])
     assert np.array_equal(pt_s, packed)
+    # every row: oracle ciphertext of each distinct value, gathered by rank
+    table = oracle.ecb_encrypt(col.key, wl.pack_int64_blocks(col.values), threads=8)
+    tw = torch.from_numpy(np.ascontiguousarray(table).view("<i8").reshape(-1, 2)).to(DEV)
+    for k, ck in enumerate((c0, c1)):             # 1-D gathers (2^26 rows)
+        assert torch.equal(ck, tw[:, k].contiguous().index_select(0, ranks))

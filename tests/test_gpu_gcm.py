@@ -188,3 +188,41 @@ def test_gcm_4gib_linearity_and_samples(oracle):
         expected = _xor(expected, oracle.gf128_mul(d, _pow(oracle, h, m - i + 1)).tobytes())
     _, t2 = am.gcm_encrypt(ks, iv, x, aad, out=out, ws=ws)
     assert _xor(t1, _np(t2).tobytes()) == expected
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(os.environ.get("AESMI_FULL_COMPARE") != "1",
+                    reason="the oracle's 4 GiB keystream takes about a minute of host CPU; "
+                           "run with AESMI_FULL_COMPARE=1")
+def test_gcm_4gib_exact_tag(oracle):
+    """4 GiB AES-128-GCM with the plaintext set to the oracle's own keystream
+    (counters 2, 3, ...): every ciphertext byte must be 0, and the tag is then
+    E(J0) ^ GHASH_A * H^(c+1) ^ L * H (c = 2^28 ciphertext blocks), computed
+    from the oracle's block cipher and GF(2^128) product alone."""
+    n = 4 << 30
+    na = 48
+    g = _rng(0x6C43)
+    key, iv, aad = g.bytes(16), g.bytes(12), g.bytes(na)
+    x = torch.empty(n, dtype=torch.uint8, device="cuda")
+    piece = 256 << 20
+    zeros = np.zeros(piece, np.uint8)
+    threads = min(16, os.cpu_count() or 1)
+    for off in range(0, n, piece):
+        ks_piece = oracle.ctr_xcrypt(key, iv, 2 + off // 16, zeros, threads=threads)
+        x[off:off + piece].copy_(torch.from_numpy(ks_piece))
+    ks = am.key_schedule(key)
+    out = torch.empty_like(x)
+    ws = torch.empty(am.gcm_workspace_bytes(na, n), dtype=torch.uint8, device="cuda")
+    _, tag = am.gcm_encrypt(ks, iv, x, aad, out=out, ws=ws)
+    assert int(torch.count_nonzero(out).item()) == 0
+    h = oracle.ecb_encrypt(key, np.zeros(16, np.uint8)).tobytes()
+    ej0 = oracle.ecb_encrypt(key, np.frombuffer(iv + b"\0\0\0\1", np.uint8)).tobytes()
+    ya = oracle.ghash(h, np.frombuffer(aad, np.uint8)).tobytes()
+    c = n // 16
+    lens = (8 * na).to_bytes(8, "big") + (8 * n).to_bytes(8, "big")
+    expected = _xor(_xor(ej0, oracle.gf128_mul(ya, _pow(oracle, h, c + 1)).tobytes()),
+                    oracle.gf128_mul(lens, h).tobytes())
+    assert _np(tag).tobytes() == expected
+    # decryption of the all-zero ciphertext gives the keystream back, same tag
+    back, tag2 = am.gcm_decrypt(ks, iv, out, aad, out=out, ws=ws)
+    assert torch.equal(back, x) and _np(tag2).tobytes() == expected
