@@ -22,8 +22,8 @@ The many-rows-at-once framing is the paper's (sec. II-III: many short
 messages, each with its own IV and key); the scheduling is this library's.
 
 The executor (what runs a batch) is pluggable: ``GpuExecutor`` launches the
-HIP kernels; the tests drive the same loop with a CPU executor that computes
-results with the oracle, to check admission, caching and accounting without a
+HIP kernels; the CPU tests drive the same loop with an executor of their own
+(tests/test_serve_cpu.py) to check admission, caching and accounting without a
 GPU.
 """
 from __future__ import annotations
@@ -416,54 +416,6 @@ class GpuExecutor:
             fb = self.filled_by.get(sl)
             if fb is not None and fb[0] is h["slot"]:
                 del self.filled_by[sl]
-
-    def idle(self):
-        pass
-
-
-class OracleExecutor:
-    """CPU executor for tests: results from the CPU oracle, completion after a
-    modelled device time (launch latency + bytes / rate) on the server clock."""
-
-    def __init__(self, oracle, pool: np.ndarray, keys: list, nslots: int, clock,
-                 nstreams: int = 2, latency_s: float = 20e-6, rate_Bps: float = 1e9):
-        self.o, self.pool, self.keys = oracle, pool, keys
-        self.clock = clock
-        self.latency, self.rate = latency_s, rate_Bps
-        self.nstreams = nstreams
-        self.busy = 0
-        self.resident = {}      # key slot -> key id whose schedule is "on the device"
-        self.fill_log = []
-        self.next_free = 0.0
-
-    def free_slots(self):
-        return self.nstreams - self.busy
-
-    def submit(self, reqs, first, last, key_slots, fills):
-        self.busy += 1
-        for sl, kid in fills:
-            self.resident[sl] = kid
-            self.fill_log.append((sl, kid))
-        outs = []
-        for j, i in enumerate(range(first, last)):
-            kid = self.resident[int(key_slots[j])]
-            assert kid == reqs.key_id[i], "key cache handed out a stale slot"
-            a, n = int(reqs.in_off[i]), int(reqs.size[i])
-            outs.append(self.o.ctr_xcrypt(self.keys[kid], reqs.nonce[i].tobytes(),
-                                          int(reqs.ctr0[i]), self.pool[a:a + n]))
-        start = max(self.clock(), self.next_free)
-        t_done = start + self.latency + int(reqs.size[first:last].sum()) / self.rate
-        self.next_free = t_done
-        return {"t": t_done, "outs": outs}
-
-    def done(self, h):
-        return self.clock() >= h["t"]
-
-    def output(self, h, j):
-        return h["outs"][j]
-
-    def release(self, h):
-        self.busy -= 1
 
     def idle(self):
         pass

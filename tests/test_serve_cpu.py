@@ -24,6 +24,54 @@ class StepClock:
         return self.t
 
 
+class OracleExecutor:
+    """CPU executor for tests: results from the CPU oracle, completion after a
+    modelled device time (launch latency + bytes / rate) on the server clock."""
+
+    def __init__(self, oracle, pool: np.ndarray, keys: list, nslots: int, clock,
+                 nstreams: int = 2, latency_s: float = 20e-6, rate_Bps: float = 1e9):
+        self.o, self.pool, self.keys = oracle, pool, keys
+        self.clock = clock
+        self.latency, self.rate = latency_s, rate_Bps
+        self.nstreams = nstreams
+        self.busy = 0
+        self.resident = {}      # key slot -> key id whose schedule is "on the device"
+        self.fill_log = []
+        self.next_free = 0.0
+
+    def free_slots(self):
+        return self.nstreams - self.busy
+
+    def submit(self, reqs, first, last, key_slots, fills):
+        self.busy += 1
+        for sl, kid in fills:
+            self.resident[sl] = kid
+            self.fill_log.append((sl, kid))
+        outs = []
+        for j, i in enumerate(range(first, last)):
+            kid = self.resident[int(key_slots[j])]
+            assert kid == reqs.key_id[i], "key cache handed out a stale slot"
+            a, n = int(reqs.in_off[i]), int(reqs.size[i])
+            outs.append(self.o.ctr_xcrypt(self.keys[kid], reqs.nonce[i].tobytes(),
+                                          int(reqs.ctr0[i]), self.pool[a:a + n]))
+        start = max(self.clock(), self.next_free)
+        t_done = start + self.latency + int(reqs.size[first:last].sum()) / self.rate
+        self.next_free = t_done
+        return {"t": t_done, "outs": outs}
+
+    def done(self, h):
+        return self.clock() >= h["t"]
+
+    def output(self, h, j):
+        return h["outs"][j]
+
+    def release(self, h):
+        self.busy -= 1
+
+    def idle(self):
+        pass
+
+
 def make_requests(n=300, nkeys=20, pool_bytes=1 << 20, rate=2e5, seed=3, big=()):
     rs = wl.serving_inputs(n, rate, nkeys=nkeys, median=1024, sigma=1.5, max_size=64 << 10,
                            seed=seed)
@@ -39,7 +87,7 @@ def make_requests(n=300, nkeys=20, pool_bytes=1 << 20, rate=2e5, seed=3, big=())
 def run(oracle, reqs, pool, keys, nslots=4, budget=256 << 10, **kw):
     clock = StepClock()
     kc = serve.KeyCache(nslots, len(keys))
-    ex = serve.OracleExecutor(oracle, pool, keys, nslots, clock, latency_s=30e-6, rate_Bps=2e9)
+    ex = OracleExecutor(oracle, pool, keys, nslots, clock, latency_s=30e-6, rate_Bps=2e9)
     srv = serve.Server(ex, kc, budget, clock=clock, **kw)
     st, res = srv.run(reqs)
     return st, res, kc, ex
