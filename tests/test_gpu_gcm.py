@@ -57,13 +57,14 @@ def test_gcm_spec_vectors(case):
 
 
 # (key bytes, message bytes, AAD bytes): GHASH block counts from 1 (empty) to
-# ~2^18 cover the final wave alone, one and several narrow passes, ragged A
-# and C tails and zero-length parts.
+# ~2^20 cover the final wave alone, one and several narrow passes, the wide
+# pass over A, ragged A and C tails and zero-length parts.
 CASES = [(16, 0, 0), (16, 1, 0), (16, 0, 1), (16, 15, 13), (16, 16, 16), (16, 17, 17),
          (24, 31, 0), (32, 1000, 100), (16, 16 * 62, 0), (16, 16 * 63, 16), (16, 16 * 64, 0),
          (16, 16 * 63 + 1, 15), (32, 4096 + 7, 4096 + 5), (16, 65536 + 3, 0),
          (24, 16 * 1023, 16), (16, 16 * 1024, 0), (16, (1 << 20) + 9, 33),
-         (32, (1 << 22) - 5, 1 << 12)]
+         (32, (1 << 22) - 5, 1 << 12),
+         (16, 33, (1 << 24) + 3)]          # AAD through the wide pass, ragged A tail
 
 
 @pytest.mark.parametrize("kb,n,na", CASES)
