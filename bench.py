@@ -46,6 +46,9 @@ def parse():
                    default="ctr",
                    help="operation of the stream leg (the headline metric is ctr)")
     p.add_argument("--key-bytes", type=int, default=16, choices=[16, 24, 32])
+    p.add_argument("--ctr-precompute", type=int, default=0, choices=[0, 1, 2],
+                   help="CTR with the table layout: 0 = rounds 1-2 precomputed (default), "
+                        "1 = round-1 nonce terms only, 2 = none (the measured baseline)")
     p.add_argument("--mode", choices=["aes", "copy"], default="aes",
                    help="copy: time a plain device copy of the same buffer instead "
                         "(reference for HBM counter calibration)")
@@ -274,6 +277,8 @@ def main():
     y = torch.empty_like(x)
     ks = am.key_schedule(inp.key, dev)
     kw = {} if layout == am.LAYOUT_AUTO else {"layout": layout}
+    if args.ctr_precompute:
+        kw["ctr_precompute"] = args.ctr_precompute
     if args.op.startswith("gcm"):
         gws = torch.empty(am.gcm_workspace_bytes(0, inp.nbytes), dtype=torch.uint8, device=dev)
         gtag = torch.empty(16, dtype=torch.uint8, device=dev)
@@ -323,8 +328,11 @@ def main():
                    ("gcm-dec", False): "gcm step (ghash passes + ctr_grouped_kernel)"}[
                        (args.op, args.layout == "bitslice")]
     # counters were taken for the default workload only (AES-128 CTR, 4 GiB)
-    default_cfg = (args.op, args.key_bytes, args.nbytes, args.layout) == ("ctr", 16, 4 << 30,
-                                                                           "auto")
+    if args.op == "ctr" and args.layout != "bitslice" and args.ctr_precompute:
+        kernel_name = "ctr_ttable_kernel<4, %s>" % ("true" if args.ctr_precompute == 1
+                                                    else "false")
+    default_cfg = (args.op, args.key_bytes, args.nbytes, args.layout,
+                   args.ctr_precompute) == ("ctr", 16, 4 << 30, "auto", 0)
     traffic = load_traffic(args.traffic_json, kernel_name) if default_cfg else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -335,7 +343,9 @@ def main():
         # 16 (Nr - 2) (rounds 1-2 come from per-thread and per-256-counter
         # group precomputation); ECB: 16 Nr -- against 32 reads/clk/CU.
         nr = {16: 10, 24: 12, 32: 14}[args.key_bytes]
-        lds_reads = (16 * (nr - 2) if args.op == "ctr" else 16 * nr) * nblocks
+        per_block = {0: 16 * (nr - 2), 1: 16 * nr - 12, 2: 16 * nr}[args.ctr_precompute] \
+            if args.op == "ctr" else 16 * nr
+        lds_reads = per_block * nblocks
         roofline["lds_treads_per_s"] = round(lds_reads / (avg_ms * 1e-3) / 1e12, 3)
         roofline["lds_frac_at_2p4ghz"] = round(lds_reads / (avg_ms * 1e-3) / 1e12
                                                / LDS_PEAK_TREADS, 4)
@@ -356,7 +366,8 @@ def main():
            "config": {"workload": "aes%d-%s-%dMiB" % (8 * args.key_bytes, args.op,
                                                          args.nbytes >> 20),
                       "nbytes": inp.nbytes,
-                      "blocks": nblocks, "layout": args.layout, "in_place": False},
+                      "blocks": nblocks, "layout": args.layout, "in_place": False,
+                      "ctr_precompute": args.ctr_precompute},
            "roofline": roofline}
     if not args.no_gcm and default_cfg:
         out["gcm"] = gcm_leg(am, ks, inp.nonce, x, y)

@@ -77,6 +77,14 @@ typedef struct aes_launch {
     uint32_t wg_size;         /* threads per workgroup (multiple of 64, <= 1024) */
     uint32_t grid_per_cu;     /* workgroups per compute unit                     */
     uint32_t blocks_per_lane; /* 16-byte blocks a lane carries per iteration     */
+    uint32_t ctr_precompute;  /* CTR with the table layout only (ignored elsewhere):
+                                 0 = default: the round-1 terms of the nonce
+                                     columns once per thread and, with four
+                                     blocks per lane, round 2 per 256-counter
+                                     group (16 (Nr - 2) table reads per block);
+                                 1 = round-1 nonce terms only (16 Nr - 12);
+                                 2 = none, every round from the counter block
+                                     (16 Nr).  The output is the same.       */
 } aes_launch_t;
 
 /*

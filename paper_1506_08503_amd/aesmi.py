@@ -48,7 +48,8 @@ class KeySchedule(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_uint32), ("wg_size", ctypes.c_uint32),
-                ("grid_per_cu", ctypes.c_uint32), ("blocks_per_lane", ctypes.c_uint32)]
+                ("grid_per_cu", ctypes.c_uint32), ("blocks_per_lane", ctypes.c_uint32),
+                ("ctr_precompute", ctypes.c_uint32)]
 
 
 class Segment(ctypes.Structure):
@@ -176,10 +177,10 @@ def expand_keys_device(keys: torch.Tensor) -> torch.Tensor:
     return out
 
 
-def _launch(layout=None, wg_size=0, grid_per_cu=0, blocks_per_lane=0):
-    if layout is None and not (wg_size or grid_per_cu or blocks_per_lane):
+def _launch(layout=None, wg_size=0, grid_per_cu=0, blocks_per_lane=0, ctr_precompute=0):
+    if layout is None and not (wg_size or grid_per_cu or blocks_per_lane or ctr_precompute):
         return None
-    return Launch(layout or 0, wg_size, grid_per_cu, blocks_per_lane)
+    return Launch(layout or 0, wg_size, grid_per_cu, blocks_per_lane, ctr_precompute)
 
 
 def _ks_arg(ks: torch.Tensor):

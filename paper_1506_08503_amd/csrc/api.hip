@@ -90,6 +90,8 @@ bool valid_launch(const aes_launch_t *launch)
         return false;
     if (launch->grid_per_cu > 64)
         return false;
+    if (launch->ctr_precompute > 2)
+        return false;
     return true;
 }
 

@@ -52,7 +52,10 @@ __global__ __launch_bounds__(1024) void ecb_ttable_kernel(
     }
 }
 
-template <int NR, int BPL>
+// PRE: the round-1 terms of the nonce columns once per thread (true) or every
+// round from the full counter block (false, the measured baseline of the
+// precomputation).
+template <int NR, int BPL, bool PRE>
 __device__ void ctr_body(const aes_key_schedule_t *__restrict__ ks,
                          const u32x4 *__restrict__ in, u32x4 *__restrict__ out,
                          uint64_t nbytes, uint32_t n0, uint32_t n1, uint32_t n2,
@@ -69,12 +72,21 @@ __device__ void ctr_body(const aes_key_schedule_t *__restrict__ ks,
     const uint64_t wg = blockDim.x;
     const uint64_t tile = wg * BPL;
     const uint64_t ntiles = nfull / tile;
-    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
-        ctr_blocks<NR, BPL>(rk, in, out, t * tile + threadIdx.x, wg, ctr0, p0, p1, p2, p3,
-                            lds, lc);
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        if (PRE)
+            ctr_blocks<NR, BPL>(rk, in, out, t * tile + threadIdx.x, wg, ctr0, p0, p1, p2, p3,
+                                lds, lc);
+        else
+            ctr_blocks_plain<NR, BPL>(rk, in, out, t * tile + threadIdx.x, wg, ctr0, u0, u1,
+                                      u2, lds, lc);
+    }
     for (uint64_t i = ntiles * tile + (uint64_t)blockIdx.x * wg + threadIdx.x; i < nfull;
-         i += (uint64_t)gridDim.x * wg)
-        ctr_blocks<NR, 1>(rk, in, out, i, 0, ctr0, p0, p1, p2, p3, lds, lc);
+         i += (uint64_t)gridDim.x * wg) {
+        if (PRE)
+            ctr_blocks<NR, 1>(rk, in, out, i, 0, ctr0, p0, p1, p2, p3, lds, lc);
+        else
+            ctr_blocks_plain<NR, 1>(rk, in, out, i, 0, ctr0, u0, u1, u2, lds, lc);
+    }
 
     // Ragged tail: the first (nbytes % 16) bytes of block nfull.
     const uint32_t tail = (uint32_t)(nbytes & 15u);
@@ -166,7 +178,7 @@ __global__ __launch_bounds__(1024) void ctr_grouped_kernel(
     }
 }
 
-template <int BPL>
+template <int BPL, bool PRE>
 __global__ __launch_bounds__(1024) void ctr_ttable_kernel(
     const aes_key_schedule_t *__restrict__ ks, const u32x4 *__restrict__ in,
     u32x4 *__restrict__ out, uint64_t nbytes, uint32_t n0, uint32_t n1, uint32_t n2,
@@ -177,9 +189,9 @@ __global__ __launch_bounds__(1024) void ctr_ttable_kernel(
     __syncthreads();
     const Lc lc = make_lc(threadIdx.x & 63u);
     switch (ks->nr) {
-    case 10: ctr_body<10, BPL>(ks, in, out, nbytes, n0, n1, n2, ctr0, lds, lc); break;
-    case 12: ctr_body<12, BPL>(ks, in, out, nbytes, n0, n1, n2, ctr0, lds, lc); break;
-    case 14: ctr_body<14, BPL>(ks, in, out, nbytes, n0, n1, n2, ctr0, lds, lc); break;
+    case 10: ctr_body<10, BPL, PRE>(ks, in, out, nbytes, n0, n1, n2, ctr0, lds, lc); break;
+    case 12: ctr_body<12, BPL, PRE>(ks, in, out, nbytes, n0, n1, n2, ctr0, lds, lc); break;
+    case 14: ctr_body<14, BPL, PRE>(ks, in, out, nbytes, n0, n1, n2, ctr0, lds, lc); break;
     default: break;
     }
 }
@@ -257,15 +269,23 @@ hipError_t ttable_ctr(const aes_key_schedule_t *ks, const uint32_t nonce_words[3
         return hipErrorInvalidConfiguration;
     const u32x4 *src = static_cast<const u32x4 *>(in);
     u32x4 *dst = static_cast<u32x4 *>(out);
-#define LAUNCH_CTR(B)                                                                    \
-    hipLaunchKernelGGL((ctr_ttable_kernel<B>), dim3(sh.grid), dim3(sh.wg), 0, stream, ks, \
-                       src, dst, nbytes, nonce_words[0], nonce_words[1], nonce_words[2],  \
+#define LAUNCH_CTR(B, P)                                                                   \
+    hipLaunchKernelGGL((ctr_ttable_kernel<B, P>), dim3(sh.grid), dim3(sh.wg), 0, stream, ks, \
+                       src, dst, nbytes, nonce_words[0], nonce_words[1], nonce_words[2],     \
                        ctr0)
-    if (sh.bpl == 1) LAUNCH_CTR(1);
-    else if (sh.bpl == 2) LAUNCH_CTR(2);
-    else
+    const uint32_t pre = launch ? launch->ctr_precompute : 0u;
+    if (pre == 2) {                       // no precomputation
+        if (sh.bpl == 1) LAUNCH_CTR(1, false);
+        else if (sh.bpl == 2) LAUNCH_CTR(2, false);
+        else LAUNCH_CTR(4, false);
+    } else if (pre == 1 || sh.bpl != 4) { // round-1 nonce terms only
+        if (sh.bpl == 1) LAUNCH_CTR(1, true);
+        else if (sh.bpl == 2) LAUNCH_CTR(2, true);
+        else LAUNCH_CTR(4, true);
+    } else {                              // rounds 1 and 2 (256-counter groups)
         hipLaunchKernelGGL(ctr_grouped_kernel, dim3(sh.grid), dim3(sh.wg), 0, stream, ks, src,
                            dst, nbytes, nonce_words[0], nonce_words[1], nonce_words[2], ctr0);
+    }
 #undef LAUNCH_CTR
     return hipGetLastError();
 }

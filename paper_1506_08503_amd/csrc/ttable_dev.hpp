@@ -288,6 +288,35 @@ __device__ __forceinline__ void ctr_blocks(const uint32_t *rk, const u32x4 *__re
                                     out + first + b * stride);
 }
 
+// The same keystream with no precomputation: every round, round 1 included,
+// from the full counter block (u0..u2 are the nonce words XOR round key 0).
+template <int NR, int BPL>
+__device__ __forceinline__ void ctr_blocks_plain(const uint32_t *rk,
+                                                 const u32x4 *__restrict__ in,
+                                                 u32x4 *__restrict__ out, uint64_t first,
+                                                 uint64_t stride, uint32_t ctr0, uint32_t u0,
+                                                 uint32_t u1, uint32_t u2, const char *lds,
+                                                 const Lc &lc)
+{
+    uint32_t s[BPL][4];
+    u32x4 x[BPL];
+#pragma unroll
+    for (int b = 0; b < BPL; ++b) {
+        const uint64_t i = first + b * stride;
+        x[b] = __builtin_nontemporal_load(in + i);
+        s[b][0] = u0;
+        s[b][1] = u1;
+        s[b][2] = u2;
+        s[b][3] = bswap32(ctr0 + (uint32_t)i) ^ rk[3];
+    }
+    enc_rounds<NR, 1, BPL>(s, rk, lds, lc);
+#pragma unroll
+    for (int b = 0; b < BPL; ++b)
+        __builtin_nontemporal_store(u32x4{x[b].x ^ s[b][0], x[b].y ^ s[b][1],
+                                          x[b].z ^ s[b][2], x[b].w ^ s[b][3]},
+                                    out + first + b * stride);
+}
+
 // Counter groups.  Write the counter of block i as c = ctr0 + i and let the
 // blocks of one wave be the 256 counters sharing c >> 8 (four per lane, lane
 // l taking low bytes l, l + 64, l + 128, l + 192).  After the initial key

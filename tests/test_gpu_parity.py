@@ -235,6 +235,27 @@ def test_device_key_expansion(oracle, key_bytes):
     assert am.expand_keys_device(_to_dev(np.zeros((0, key_bytes), np.uint8))).numel() == 0
 
 
+@pytest.mark.parametrize("pre", [0, 1, 2])
+@pytest.mark.parametrize("bpl", [1, 2, 4])
+def test_ctr_precompute_variants(oracle, keys, pre, bpl):
+    """Each counter-precomputation option (rounds 1-2 per 256-counter group,
+    round-1 nonce terms, none) with each blocks-per-lane count gives the same
+    keystream as the oracle, for all key sizes, counters starting inside a
+    group and ragged tails."""
+    g = _rng(1000 + 10 * pre + bpl)
+    nbytes = 16 * (1024 * 4 * 3 + 517) + 5
+    pt = np.frombuffer(g.bytes(nbytes), np.uint8)
+    for key_bytes in (16, 24, 32):
+        key = keys[key_bytes]
+        ks = am.key_schedule(key)
+        for ctr0 in (0, 200, 2 ** 32 - nbytes // 16 - 1):
+            nonce = g.bytes(12)
+            got = am.ctr_xcrypt(ks, nonce, ctr0, _to_dev(pt), layout=am.LAYOUT_TTABLE,
+                                blocks_per_lane=bpl, ctr_precompute=pre)
+            assert np.array_equal(_host(got), oracle.ctr_xcrypt(key, nonce, ctr0, pt)), \
+                (key_bytes, ctr0)
+
+
 # -------------------------------------------------------------- 4 GiB stream
 def sample_indices(nblocks, g, nrandom=100_000, tile=2048):
     edges = np.concatenate([np.arange(4096), nblocks - 1 - np.arange(4096),
@@ -280,6 +301,23 @@ def test_stream_4gib_sampled(oracle):
     x2 = x.clone()
     am.ctr_xcrypt(ks, inp.nonce, inp.ctr0, x2, out=x2)
     assert torch.equal(x2, y)
+
+
+@pytest.mark.slow
+def test_stream_sharded_equals_whole():
+    """The multi-GPU split (block range g of G with ctr0 + start_g), run on one
+    GPU: eight 512 MiB shards give the same 4 GiB output as one call."""
+    inp = wl.stream_4g_inputs()
+    x = fill_device(inp)
+    ks = am.key_schedule(inp.key)
+    whole = am.ctr_xcrypt(ks, inp.nonce, inp.ctr0, x)
+    shard = inp.nbytes // 8
+    out = torch.empty_like(x)
+    for gidx in range(8):
+        lo = gidx * shard
+        am.ctr_xcrypt(ks, inp.nonce, inp.ctr0 + lo // 16, x[lo:lo + shard],
+                      out=out[lo:lo + shard])
+    assert torch.equal(out, whole)
 
 
 @pytest.mark.slow

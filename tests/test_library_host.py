@@ -104,6 +104,8 @@ def test_ctr_validation():
     assert f(ks, nonce, 2 ** 32 - 2, a, b, 33, None) == -6
     bad = am.Launch(0, 2048, 0, 0)
     assert L.aes_ctr_xcrypt_ex(ks, nonce, 0, a, b, 16, ctypes.byref(bad), None) == -9
+    bad = am.Launch(1, 0, 0, 4, 3)                      # ctr_precompute is 0, 1 or 2
+    assert L.aes_ctr_xcrypt_ex(ks, nonce, 0, a, b, 16, ctypes.byref(bad), None) == -9
     # status strings
     for code, name in am.STATUS.items():
         assert L.aes_status_string(code)
