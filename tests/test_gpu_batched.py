@@ -181,6 +181,43 @@ def test_batched_invalid_key_schedule(oracle, tune):
             assert np.array_equal(o[a:a + ln], exp), i
 
 
+@pytest.mark.parametrize("nsegs,pattern", [(9, "empties"), (20000, "many")])
+def test_batched_empty_runs_and_large_tables(oracle, nsegs, pattern):
+    """Runs of empty segments (at the start, inside and at the end of the
+    table: they share their tile start with the next segment), and a table
+    larger than the prepare kernel keeps in LDS (tile counts then go through
+    global memory)."""
+    g = _rng(11 + nsegs)
+    if pattern == "empties":
+        lengths = np.array([0, 0, 100, 0, 0, 16 * 5000 + 3, 0, 0, 0], np.int64)
+    else:
+        lengths = g.integers(0, 600, size=nsegs).astype(np.int64)
+        lengths[::7] = 0
+        lengths[-50:] = 0
+    n = lengths.size
+    in_off, total = wl.pack_offsets(lengths)
+    keys = [g.bytes(16) for _ in range(4)]
+    slots = g.integers(0, 4, size=n).astype(np.uint32)
+    nonces = np.frombuffer(g.bytes(12 * n), np.uint8).reshape(n, 12)
+    ctr0 = g.integers(0, 2 ** 20, size=n).astype(np.uint32)
+    segs_h = bt.segment_table(in_off, in_off, lengths, slots, ctr0, nonces)
+    pt = np.frombuffer(g.bytes(total + 16), np.uint8).copy()
+    x = torch.from_numpy(pt).to(DEV)
+    out = torch.full_like(x, 0x5A)
+    ws = bt.workspace(n, DEV)
+    am.ctr_xcrypt_batched(torch.from_numpy(segs_h.view(np.uint8).copy()).to(DEV),
+                          key_table(keys), x, out, ws)
+    assert am.batched_read_status(ws) == 0
+    o = out.cpu().numpy()
+    exp = np.full_like(pt, 0x5A)
+    for i in range(n):
+        a, ln = int(in_off[i]), int(lengths[i])
+        if ln:
+            exp[a:a + ln] = oracle.ctr_xcrypt(keys[slots[i]], nonces[i].tobytes(), int(ctr0[i]),
+                                              pt[a:a + ln])
+    assert np.array_equal(o, exp)
+
+
 def test_batched_graph_replays(mixed):
     """A captured graph replayed three times, the input rewritten in place with
     eager work and synchronizations in between; every replay equals an eager
