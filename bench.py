@@ -32,13 +32,18 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 lanes x 2.4 GHz, 32-bit ops
 LDS_PEAK_TREADS = 256 * 32 * 2.4e9 / 1e12  # 32 dword reads per clock per CU
+WARM_MS = 150                  # default warm-up length (see --warmup)
 
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=-1,
+                   help="untimed steps before the timed ones; the default (-1) runs steps "
+                        "until %d ms have passed (at least 3): after idle the chip takes "
+                        "tens of milliseconds under load to reach its working clock"
+                        % WARM_MS)
     p.add_argument("--nbytes", type=int, default=4 << 30)
     p.add_argument("--layout", choices=["auto", "ttable", "bitslice"], default="auto")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -64,6 +69,17 @@ def parse():
     return p.parse_args()
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(inp, threads):
     """Oracle CTR (as it stands) on a bounded prefix of the same plaintext:
     48 MiB per host thread, about 10 s of CPU work on the benchmark host."""
@@ -76,7 +92,7 @@ def cpu_baseline(inp, threads):
     o.ctr_xcrypt(inp.key, inp.nonce, inp.ctr0, g, threads=threads)
     dt = time.perf_counter() - t0
     return {"value": round(sample / dt / 1e9, 6), "unit": "GB/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "host": "%s, %d cpus" % (_cpu_model(), os.cpu_count() or 0),
             "sample": "first %d MiB of the 4 GiB AES-128-CTR plaintext, %d host threads, "
                       "%.2f s" % (sample >> 20, threads, dt)}
 
@@ -182,9 +198,15 @@ def sweep_fig3():
         y = torch.empty_like(x)
         z = torch.empty_like(x)
         reps = 20 if n < (64 << 20) else 5
-        t_enc = autotune.time_launch(lambda: am.cbc_encrypt(ks, iv, x, nmsg, out=y), reps)
-        t_dec = autotune.time_launch(lambda: am.cbc_decrypt(ks, iv, y, nmsg, out=z), reps)
-        t_ctr = autotune.time_launch(lambda: am.ctr_xcrypt(ks, b"\0" * 12, 0, x, out=z), reps)
+        enc = lambda: am.cbc_encrypt(ks, iv, x, nmsg, out=y)
+        dec = lambda: am.cbc_decrypt(ks, iv, y, nmsg, out=z)
+        ctr = lambda: am.ctr_xcrypt(ks, b"\0" * 12, 0, x, out=z)
+        warm(torch, enc)
+        t_enc = autotune.time_launch(enc, reps)
+        warm(torch, dec)
+        t_dec = autotune.time_launch(dec, reps)
+        warm(torch, ctr)
+        t_ctr = autotune.time_launch(ctr, reps)
         assert torch.equal(am.cbc_decrypt(ks, iv, y, nmsg), x)
         return {"messages": nmsg, "msg_bytes": msg_bytes, "total_bytes": n,
                 "cbc_enc_GBps": round(n / t_enc / 1e6, 3), "cbc_dec_GBps": round(n / t_dec / 1e6, 3),
@@ -195,6 +217,19 @@ def sweep_fig3():
     for e in range(4, 21, 2):                      # 128 messages of 16 B .. 1 MiB
         rows.append(dict(measure(128, 1 << e), curve="128 messages"))
     return {"sweep": "paper Fig. 3 workloads, AES-128", "rows": rows}
+
+
+def warm(torch, fn, ms=WARM_MS):
+    """Call fn until ms milliseconds have passed (at least three calls) and
+    return the number of calls: after idle the chip takes tens of
+    milliseconds under load to reach its working clock."""
+    n = 0
+    t0 = time.perf_counter()
+    while n < 3 or (time.perf_counter() - t0) * 1e3 < ms:
+        fn()
+        torch.cuda.synchronize()
+        n += 1
+    return n
 
 
 def _event_ms(torch, fn, steps, warmup=2):
@@ -297,8 +332,11 @@ def main():
         else:
             am.ctr_xcrypt(ks, inp.nonce, inp.ctr0, x, out=y, **kw)
 
-    for _ in range(args.warmup):
-        step()
+    if args.warmup >= 0:
+        for _ in range(args.warmup):
+            step()
+    else:
+        args.warmup = warm(torch, step)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream(dev)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))

@@ -75,7 +75,11 @@ typedef enum {
 typedef struct aes_launch {
     uint32_t layout;          /* aes_layout_t                                    */
     uint32_t wg_size;         /* threads per workgroup (multiple of 64, <= 1024) */
-    uint32_t grid_per_cu;     /* workgroups per compute unit                     */
+    uint32_t grid_per_cu;     /* workgroups per compute unit, at most 64.  The
+                                 default sizes the grid from the input: table
+                                 layout, one per CU up to 16384 blocks per wave
+                                 and more beyond; bitsliced, one 2048-block
+                                 batch per wave (at most 64 per CU)          */
     uint32_t blocks_per_lane; /* 16-byte blocks a lane carries per iteration     */
     uint32_t ctr_precompute;  /* CTR with the table layout only (ignored elsewhere):
                                  0 = default: the round-1 terms of the nonce
