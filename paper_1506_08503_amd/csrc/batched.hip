@@ -153,6 +153,11 @@ __device__ __forceinline__ uint32_t find_segment(const uint32_t *__restrict__ st
     return lo;
 }
 
+// One tile per atomic add.  The single counter serializes the adds (about
+// 13 ns each, measured), which caps a launch near 75 M tiles/s: tiles of
+// 2048 blocks keep well below that.  Claiming chunks of consecutive tiles
+// per add lifted the cap but was slower at 2048-4096 blocks per tile (waves
+// then stream through separate regions instead of neighbouring tiles).
 __device__ __forceinline__ uint32_t claim_tile(WsHeader *h, uint32_t lane)
 {
     uint32_t t = 0;
@@ -235,13 +240,19 @@ __device__ void ttable_tile(const TileJob &j, const char *lds, const Lc &lc, uin
                           lds, lc);
     for (uint64_t i = b + lane; i < hi; i += 64)
         ctr_blocks<NR, 1>(rk, j.in, j.out, i, 0, j.ctr0, pre[0], pre[1], pre[2], pre[3], lds, lc);
-    if (j.tail && j.b1 == j.nfull + 1 && lane == 0) {
+    if (j.tail && j.b1 == j.nfull + 1) {
+        // The partial last block: lane k < tail computes the keystream block
+        // and handles byte k, so the bytes go out in one load and one store
+        // instead of a loop of dependent byte accesses on one lane.
         uint32_t s1[1][4] = {{u0, u1, u2, bswap32(j.ctr0 + (uint32_t)j.nfull) ^ rk[3]}};
         enc_rounds<NR, 1, 1>(s1, rk, lds, lc);
-        const uint8_t *src = reinterpret_cast<const uint8_t *>(j.in + j.nfull);
-        uint8_t *dst = reinterpret_cast<uint8_t *>(j.out + j.nfull);
-        for (uint32_t k = 0; k < j.tail; ++k)
-            dst[k] = src[k] ^ (uint8_t)(s1[0][k >> 2] >> (8 * (k & 3u)));
+        const uint32_t k = lane & 15u;
+        const uint32_t w = k < 8u ? (k < 4u ? s1[0][0] : s1[0][1]) : (k < 12u ? s1[0][2] : s1[0][3]);
+        if (lane < j.tail) {
+            const uint8_t *src = reinterpret_cast<const uint8_t *>(j.in + j.nfull);
+            uint8_t *dst = reinterpret_cast<uint8_t *>(j.out + j.nfull);
+            dst[k] = src[k] ^ (uint8_t)(w >> (8u * (k & 3u)));
+        }
     }
 }
 

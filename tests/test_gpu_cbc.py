@@ -70,3 +70,39 @@ def test_cbc_in_place_encrypt_and_errors(oracle):
         am.cbc_decrypt(ks, iv, x, 50, out=x)
     with pytest.raises(am.AesError, match="AES_ERR_LENGTH"):
         am.cbc_encrypt(ks, iv, torch.zeros(50 * 20, dtype=torch.uint8, device=DEV), 50)
+
+
+@pytest.mark.parametrize("nmsg,msg_bytes", [((1 << 20) + 77, 16), (1_100_003, 32)])
+def test_cbc_million_rows(oracle, nmsg, msg_bytes):
+    """A million rows and more (every lane of the grid takes several rows,
+    every thread of the decryption several blocks).  Sampled rows (the first
+    and last ones, and rows on lane, workgroup and grid-stride borders)
+    against the oracle in both directions; the round trip of every row on
+    the device."""
+    g = _rng(nmsg + msg_bytes)
+    key = g.bytes(16)
+    ks = am.key_schedule(key)
+    pt = np.frombuffer(g.bytes(nmsg * msg_bytes), np.uint8).reshape(nmsg, msg_bytes)
+    ivs = np.frombuffer(g.bytes(16 * nmsg), np.uint8).reshape(nmsg, 16)
+    x = torch.from_numpy(pt.copy()).to(DEV).view(-1)
+    iv = torch.from_numpy(ivs.copy()).to(DEV).view(-1)
+    ct_d = am.cbc_encrypt(ks, iv, x, nmsg)
+    ct = ct_d.cpu().numpy().reshape(nmsg, msg_bytes)
+    rows = set(range(0, 70)) | set(range(nmsg - 70, nmsg))
+    for b in (64, 256, 1024, 2048, 4096, 1 << 18, 1 << 20):
+        for k in range(1, 4):
+            for d in (-2, -1, 0, 1):
+                r = k * b + d
+                if 0 <= r < nmsg:
+                    rows.add(r)
+    rows |= set(int(r) for r in g.integers(0, nmsg, 1500))
+    for r in sorted(rows):
+        assert np.array_equal(ct[r], oracle.cbc_encrypt(key, ivs[r].tobytes(), pt[r])), r
+    # decryption of unrelated ciphertext rows, against the oracle
+    cr = np.frombuffer(g.bytes(nmsg * msg_bytes), np.uint8).reshape(nmsg, msg_bytes)
+    dec = am.cbc_decrypt(ks, iv, torch.from_numpy(cr.copy()).to(DEV).view(-1), nmsg)
+    dec = dec.cpu().numpy().reshape(nmsg, msg_bytes)
+    for r in sorted(rows):
+        assert np.array_equal(dec[r], oracle.cbc_decrypt(key, ivs[r].tobytes(), cr[r])), r
+    back = am.cbc_decrypt(ks, iv, ct_d, nmsg)
+    assert torch.equal(back, x)
