@@ -232,8 +232,9 @@ __device__ void ttable_tile(const TileJob &j, const char *lds, const Lc &lc, uin
             r2[q][2] = TL(2, s0, 2);
             r2[q][3] = TL(1, s0, 1);
         }
-        for (; b + 256 <= hi; b += 256)
-            ctr_group<NR>(rk, j.in, j.out, b + lane, j.ctr0 + (uint32_t)b, pre, r2, lds, lc);
+        const uint64_t n = (hi - b) >> 8;
+        ctr_groups<NR>(rk, j.in, j.out, b, j.ctr0 + (uint32_t)b, n, 1, pre, r2, lds, lc, lane);
+        b += 256u * n;
     }
     for (; b + 256 <= hi; b += 256)
         ctr_blocks<NR, 4>(rk, j.in, j.out, b + lane, 64, j.ctr0, pre[0], pre[1], pre[2], pre[3],

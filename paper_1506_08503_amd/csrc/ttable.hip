@@ -141,9 +141,10 @@ __device__ void ctr_body_grouped(const aes_key_schedule_t *__restrict__ ks,
         i_hi = 256u * q_end - delta;
         const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
         const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-        for (uint64_t q = q_first + wave; q < q_end; q += waves)
-            ctr_group<NR>(rk, in, out, 256u * q - delta + lane, cbase + (uint32_t)(256u * q),
-                          pre, r2, lds, lc);
+        const uint64_t q0 = q_first + wave;
+        if (q0 < q_end)
+            ctr_groups<NR>(rk, in, out, 256u * q0 - delta, cbase + (uint32_t)(256u * q0),
+                           (q_end - q0 + waves - 1) / waves, waves, pre, r2, lds, lc, lane);
     }
     // blocks of the partial first and last groups, one per lane
     const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;

@@ -334,33 +334,44 @@ __device__ __forceinline__ void ctr_blocks_plain(const uint32_t *rk,
 // Round 2 reads one byte of round-1 column 0 per output column, the other
 // three bytes coming from columns 1..3; so round-2 output column c is
 //     Q_c(group) ^ R_c(lane, slot).
-// R is computed once per thread (16 lookups), Q once per group and wave (15
-// lookups shared by 256 blocks), and each block starts at round 3: 16 * (Nr-2)
-// lookups instead of 16 * Nr - 12.  Same cipher, bit for bit.
-template <int NR>
-__device__ __forceinline__ void ctr_group(const uint32_t *rk, const u32x4 *__restrict__ in,
-                                          u32x4 *__restrict__ out, uint64_t first, uint32_t cg,
-                                          const uint32_t (&pre)[4], const uint32_t (&r2)[4][4],
-                                          const char *lds, const Lc &lc)
+// R is computed once per thread (16 lookups) and Q once per group (15
+// lookups; lane l of a wave computes Q of the wave's (l+1)-th next group, so
+// one pass serves 64 groups, and a group reads its four words back with
+// v_readlane), and each block starts at round 3: 16 * (Nr - 2) lookups
+// instead of 16 * Nr - 12.  Same cipher, bit for bit.
+
+// Q (round-2 group words, round key 2 added) of the group whose counters
+// share the upper bytes of cg.
+__device__ __forceinline__ void ctr_group_q(uint32_t cg, const uint32_t *rk,
+                                            const uint32_t (&pre)[4], const char *lds,
+                                            const Lc &lc, uint32_t (&q)[4])
 {
-    // group constants (all lanes compute the same values)
     const uint32_t w3 = bswap32(cg) ^ rk[3];
     const uint32_t s1 = pre[1] ^ TL(2, w3, 2);
     const uint32_t s2 = pre[2] ^ TL(1, w3, 1);
     const uint32_t s3 = pre[3] ^ TL(0, w3, 0);
-    const uint32_t q0 = xor3(TL(1, s1, 1), TL(2, s2, 2), TL(3, s3, 3)) ^ rk[8];
-    const uint32_t q1 = xor3(TL(0, s1, 0), TL(1, s2, 1), TL(2, s3, 2)) ^ rk[9];
-    const uint32_t q2 = xor3(TL(0, s2, 0), TL(1, s3, 1), TL(3, s1, 3)) ^ rk[10];
-    const uint32_t q3 = xor3(TL(0, s3, 0), TL(2, s1, 2), TL(3, s2, 3)) ^ rk[11];
+    q[0] = xor3(TL(1, s1, 1), TL(2, s2, 2), TL(3, s3, 3)) ^ rk[8];
+    q[1] = xor3(TL(0, s1, 0), TL(1, s2, 1), TL(2, s3, 2)) ^ rk[9];
+    q[2] = xor3(TL(0, s2, 0), TL(1, s3, 1), TL(3, s1, 3)) ^ rk[10];
+    q[3] = xor3(TL(0, s3, 0), TL(2, s1, 2), TL(3, s2, 3)) ^ rk[11];
+}
+
+// One group of 256 counter blocks on one wave, Q given (wave-uniform).
+template <int NR>
+__device__ __forceinline__ void ctr_group(const uint32_t *rk, const u32x4 *__restrict__ in,
+                                          u32x4 *__restrict__ out, uint64_t first,
+                                          const uint32_t (&q)[4], const uint32_t (&r2)[4][4],
+                                          const char *lds, const Lc &lc)
+{
     uint32_t s[4][4];
     u32x4 x[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         x[b] = __builtin_nontemporal_load(in + first + 64 * b);
-        s[b][0] = q0 ^ r2[b][0];
-        s[b][1] = q1 ^ r2[b][1];
-        s[b][2] = q2 ^ r2[b][2];
-        s[b][3] = q3 ^ r2[b][3];
+        s[b][0] = q[0] ^ r2[b][0];
+        s[b][1] = q[1] ^ r2[b][1];
+        s[b][2] = q[2] ^ r2[b][2];
+        s[b][3] = q[3] ^ r2[b][3];
     }
     enc_rounds<NR, 3, 4>(s, rk, lds, lc);
 #pragma unroll
@@ -368,6 +379,29 @@ __device__ __forceinline__ void ctr_group(const uint32_t *rk, const u32x4 *__res
         __builtin_nontemporal_store(u32x4{x[b].x ^ s[b][0], x[b].y ^ s[b][1],
                                           x[b].z ^ s[b][2], x[b].w ^ s[b][3]},
                                     out + first + 64 * b);
+}
+
+// n groups on one wave: group k starts at block blk0 + 256 step k with
+// counter c0 + 256 step k (c0 a multiple of 256); lane l takes blocks l,
+// l + 64, l + 128 and l + 192 of each.
+template <int NR>
+__device__ __forceinline__ void ctr_groups(const uint32_t *rk, const u32x4 *__restrict__ in,
+                                           u32x4 *__restrict__ out, uint64_t blk0, uint32_t c0,
+                                           uint64_t n, uint64_t step, const uint32_t (&pre)[4],
+                                           const uint32_t (&r2)[4][4], const char *lds,
+                                           const Lc &lc, uint32_t lane)
+{
+    uint32_t qv[4] = {0, 0, 0, 0};
+    for (uint64_t k = 0; k < n; ++k) {
+        const uint32_t j = (uint32_t)k & 63u;
+        if (j == 0)   // lanes past the last group compute values nobody reads
+            ctr_group_q(c0 + (uint32_t)(256u * step * (k + lane)), rk, pre, lds, lc, qv);
+        const uint32_t qg[4] = {(uint32_t)__builtin_amdgcn_readlane((int)qv[0], (int)j),
+                                (uint32_t)__builtin_amdgcn_readlane((int)qv[1], (int)j),
+                                (uint32_t)__builtin_amdgcn_readlane((int)qv[2], (int)j),
+                                (uint32_t)__builtin_amdgcn_readlane((int)qv[3], (int)j)};
+        ctr_group<NR>(rk, in, out, blk0 + 256u * step * k + lane, qg, r2, lds, lc);
+    }
 }
 
 }  // namespace
