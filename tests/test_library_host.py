@@ -5,7 +5,9 @@ aes_status_string, aes_batched_workspace_bytes) or fails argument validation,
 which the library does before any HIP call.
 """
 import ctypes
+import os
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -183,3 +185,15 @@ def test_gcm_and_ghash_validation():
     assert L.aes_ghash(h, None, 100, tag, ws, gneed, None) == -1
     assert L.aes_ghash(h, VP(0x20008), 100, tag, ws, gneed, None) == -4
     assert L.aes_ghash(h, a, 100, tag, ws, gneed - 1, None) == -9
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message, before
+    it touches torch or the GPU."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
