@@ -13,7 +13,8 @@
  * Conventions shared by every entry point
  *  - Plain C types only.  Device buffers are raw device pointers; `stream` is
  *    a hipStream_t passed as void* (NULL = the null stream).
- *  - The caller owns every buffer.  No entry point allocates device memory.
+ *  - The caller owns every buffer.  No entry point allocates device memory,
+ *    except that aes_batched_graph_create builds a HIP graph (set-up code).
  *  - Launching entry points are stream-ordered and asynchronous: AES_OK means
  *    the arguments passed validation and the work was enqueued on `stream`.
  *    Argument errors are returned before any HIP call is made.
@@ -275,6 +276,17 @@ aes_status_t aes_batched_read_status(const void *ws_dev, void *stream,
  * Graph form of the batched call: captures aes_ctr_xcrypt_batched with fixed
  * pointers into a HIP graph.  The caller may rewrite the contents of segs_dev,
  * the input and the key table between launches (nsegs is fixed per graph).
+ *   aes_batched_graph_create  validates the arguments as the batched call
+ *       does (its error codes), records the two kernels on `stream` (on a
+ *       private stream if `stream` is NULL, which cannot be captured) and
+ *       instantiates the graph.  It allocates: the handle in host memory and
+ *       the executable graph inside the HIP runtime, so it is set-up code,
+ *       not hot-path code.  *graph_out is NULL unless AES_OK is returned; the
+ *       caller owns the handle and releases it with aes_batched_graph_destroy.
+ *   aes_batched_graph_launch  enqueues the graph on `stream` (AES_ERR_NULL for
+ *       a NULL handle, AES_ERR_HIP if the runtime refuses).
+ *   aes_batched_graph_destroy releases the graph and the handle; NULL is a
+ *       no-op.  Launches already enqueued must have completed.
  */
 typedef struct aes_batched_graph aes_batched_graph_t;
 aes_status_t aes_batched_graph_create(const aes_segment_t *segs_dev, uint32_t nsegs,
