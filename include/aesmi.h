@@ -256,10 +256,18 @@ size_t aes_batched_workspace_bytes(uint32_t nsegs);
  *   nkeys       number of schedules in ks_table_dev (key_slot must be < nkeys)
  *   ws_dev      device workspace of at least aes_batched_workspace_bytes(nsegs)
  *   tune        host pointer or NULL
- * Segment errors (bad slot, misaligned offset, counter overflow, reserved != 0)
- * are found on the device: that segment is skipped and the status word in the
- * workspace becomes AES_ERR_SEGMENT; read it after the stream completes with
+ * Segment errors (bad slot, misaligned offset, counter overflow, reserved != 0,
+ * a key schedule without a valid round count) are found on the device: that
+ * segment is skipped and the status word in the workspace becomes
+ * AES_ERR_SEGMENT; read it after the stream completes with
  * aes_batched_read_status.  Messages must not overlap each other's output.
+ * Host-side errors, returned before any launch: AES_ERR_NULL (a NULL
+ * pointer), AES_ERR_SEGMENT (nkeys == 0), AES_ERR_ALIGN (segs_dev or a base
+ * pointer not 16-byte aligned, ws_dev not 256-byte aligned), AES_ERR_CONFIG
+ * (workspace too small, or a tune field out of range: layout, wg_size a
+ * multiple of 64 up to 1024 (256 bitsliced), grid_per_cu up to 64,
+ * tile_blocks a multiple of 64 up to 2^20 (of 2048 bitsliced)).  nsegs == 0
+ * is a no-op that leaves the workspace untouched.
  */
 aes_status_t aes_ctr_xcrypt_batched(const aes_segment_t *segs_dev, uint32_t nsegs,
                                     const aes_key_schedule_t *ks_table_dev,

@@ -92,6 +92,9 @@ bool valid_launch(const aes_launch_t *launch)
         return false;
     if (launch->ctr_precompute > 2)
         return false;
+    // the bitsliced kernels run workgroups of at most 256 threads
+    if (launch->layout == AES_LAYOUT_BITSLICE && launch->wg_size > 256)
+        return false;
     return true;
 }
 
@@ -342,6 +345,9 @@ aes_status_t aes_ctr_xcrypt_batched(const aes_segment_t *segs_dev, uint32_t nseg
         if (tune->grid_per_cu > 64)
             return AES_ERR_CONFIG;
         if (tune->tile_blocks && (tune->tile_blocks % 64 || tune->tile_blocks > (1u << 20)))
+            return AES_ERR_CONFIG;
+        if (tune->layout == AES_LAYOUT_BITSLICE &&
+            (tune->wg_size > 256 || (tune->tile_blocks && tune->tile_blocks % 2048)))
             return AES_ERR_CONFIG;
     }
     return from_hip(batched_ctr(segs_dev, nsegs, ks_table_dev, nkeys, in_base_dev,

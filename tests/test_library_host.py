@@ -89,6 +89,8 @@ def test_ecb_validation():
     assert L.aes_ecb_decrypt_ex(ks, a, b, 32, ctypes.byref(bad), None) == -9
     bad = am.Launch(1, 256, 0, 3)
     assert L.aes_ecb_encrypt_ex(ks, a, b, 32, ctypes.byref(bad), None) == -9
+    bad = am.Launch(2, 512, 0, 0)                       # bitsliced: at most 256 threads
+    assert L.aes_ecb_encrypt_ex(ks, a, b, 32, ctypes.byref(bad), None) == -9
 
 
 def test_ctr_validation():
@@ -140,6 +142,10 @@ def test_batched_validation():
     assert f(segs, 10, kt, 4, a, b, None, ws, need - 1, None) == -9
     bad = am.BatchTune(0, 0, 0, 100)
     assert f(segs, 10, kt, 4, a, b, ctypes.byref(bad), ws, need, None) == -9
+    # the bitsliced layout: at most 256 threads, tiles of whole 2048-block batches
+    for bad in (am.BatchTune(am.LAYOUT_BITSLICE, 512, 0, 0),
+                am.BatchTune(am.LAYOUT_BITSLICE, 0, 0, 1024)):
+        assert f(segs, 10, kt, 4, a, b, ctypes.byref(bad), ws, need, None) == -9
     st = ctypes.c_int32(0)
     assert L.aes_batched_read_status(None, None, ctypes.byref(st)) == -1
     g = VP()
