@@ -4,8 +4,9 @@ Every segment must equal the CPU oracle's CTR of that message alone, with its
 own key, nonce and counter (tolerance 0), for both round-function layouts and
 several tile sizes; invalid segments are reported and left untouched; graph
 replays equal eager runs; the full 10,000-message workload equals a loop of
-plain per-message launches.
+plain per-message launches and the oracle on every byte.
 """
+import os
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -261,10 +262,10 @@ def test_autotune_small():
 
 @pytest.mark.slow
 def test_batched_full_workload(oracle):
-    """10,000 messages, log-uniform 1 B .. 1 MiB, own AES-128 keys and nonces:
-    one persistent launch equals 10,000 plain launches byte for byte, and the
-    oracle agrees on every message up to 64 KiB and on sampled blocks of the
-    larger ones."""
+    """10,000 messages, log-uniform 1 B .. 1 MiB, own AES-128 keys and nonces
+    (0.68 GiB): one persistent launch equals 10,000 plain launches byte for
+    byte, and the oracle agrees on every byte of every message (about 10 s on
+    16 host threads)."""
     b = wl.batched_inputs()
     db = bt.DeviceBatch(b, DEV)
     got = db.run().clone()
@@ -274,22 +275,13 @@ def test_batched_full_workload(oracle):
     assert torch.equal(got, loop)
     pt = db.x.cpu().numpy()
     out = got.cpu().numpy()
-    g = _rng(11)
-    small = [i for i in range(b.lengths.size) if b.lengths[i] <= 1 << 16]
 
-    def check_small(i):
+    def check(i):
         a, n = int(b.offsets[i]), int(b.lengths[i])
         exp = oracle.ctr_xcrypt(b.keys[i].tobytes(), b.nonces[i].tobytes(), 0, pt[a:a + n])
         return np.array_equal(out[a:a + n], exp)
-    with ThreadPoolExecutor(8) as ex:
-        assert all(ex.map(check_small, small))
-    for i in range(b.lengths.size):
-        if b.lengths[i] <= 1 << 16:
-            continue
-        a, n = int(b.offsets[i]), int(b.lengths[i])
-        nb = (n + 15) // 16
-        idx = np.unique(np.concatenate([[0, nb - 1], g.integers(0, nb, 16)])).astype(np.uint64)
-        ks = oracle.ctr_keystream_at(b.keys[i].tobytes(), b.nonces[i].tobytes(), 0, idx)
-        for j, blk in enumerate(idx.tolist()):
-            lo, hi = a + 16 * blk, min(a + 16 * blk + 16, a + n)
-            assert np.array_equal(out[lo:hi], pt[lo:hi] ^ ks[j][:hi - lo]), (i, blk)
+    # largest messages first so that the threads finish together
+    order = np.argsort(-b.lengths, kind="stable").tolist()
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        bad = [i for i, ok in zip(order, ex.map(check, order)) if not ok]
+    assert not bad, bad[:10]
