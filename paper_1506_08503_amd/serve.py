@@ -182,8 +182,11 @@ class Stats:
     max_inflight: int = 0
     max_held: int = 0
 
-    def summary(self) -> dict:
-        lat = self.latency_s[np.isfinite(self.latency_s)]
+    def summary(self, skip: int = 0) -> dict:
+        """Counts and rates of the whole run; latency percentiles over the
+        requests from index `skip` on (the ones after a warm-up period)."""
+        lat = self.latency_s[skip:]
+        lat = lat[np.isfinite(lat)]
         q = (lambda p: float(np.percentile(lat, p)) * 1e3) if lat.size else (lambda p: None)
         return {"requests": self.completed, "rejected": self.rejected,
                 "GBps": self.bytes / self.elapsed_s / 1e9 if self.elapsed_s else None,

@@ -188,3 +188,15 @@ def test_key_cache_max_prefix_is_exact():
             ok = kc.acquire(ids[:j]) is not None if j else True
             (kc.slot_of, kc.key_of, kc.last_use, kc.pins, kc.tick, kc.hits, kc.misses) = snap
             assert ok == (j <= k), (trial, j, k)
+
+
+def test_summary_skips_warmup():
+    """Latency percentiles can leave out the first requests of a run (its
+    warm-up); counts and rates still cover the whole run."""
+    st = serve.Stats(completed=6, bytes=600, batches=2, elapsed_s=1e-3)
+    st.latency_s = np.array([9e-3, 8e-3, 1e-3, 1e-3, 2e-3, np.inf])
+    s_all, s_late = st.summary(), st.summary(skip=2)
+    assert s_all["max_ms"] == pytest.approx(9.0)
+    assert s_late["max_ms"] == pytest.approx(2.0) and s_late["p50_ms"] == pytest.approx(1.0)
+    assert s_late["requests"] == s_all["requests"] == 6
+    assert s_late["GBps"] == s_all["GBps"]
