@@ -164,7 +164,8 @@ def serving_leg(nreq):
         reqs = serve.requests_from_stream(rs, pool_bytes)
         if closed:
             reqs.arrival[:] = 0.0
-        ex = serve.GpuExecutor(pool, rs.keys, nslots, nstreams=2, max_segs=8192)
+        ex = serve.GpuExecutor(pool, rs.keys, nslots, nstreams=2, max_segs=8192,
+                               out_arena_bytes=4 << 30)
         srv = serve.Server(ex, serve.KeyCache(nslots, len(rs.keys)), hbm_budget=4 << 30,
                            max_batch_reqs=8192, window_s=50e-6)
         st, _ = srv.run(reqs)

@@ -309,7 +309,7 @@ class GpuExecutor:
     length), one scatter into the key table and the two batched kernels."""
 
     def __init__(self, pool, keys: list, nslots: int, nstreams: int = 2,
-                 max_segs: int = 8192, tune=None):
+                 max_segs: int = 8192, tune=None, out_arena_bytes: int = 0):
         import torch
         from . import aesmi
         from .batch import workspace
@@ -339,6 +339,13 @@ class GpuExecutor:
                 "busy": False})
         # key slot -> (stream slot, event) of an in-flight batch that filled it
         self.filled_by = {}
+        # Batch outputs are carved from one preallocated arena while it lasts
+        # (a fresh allocation per batch cost ~70 us of host time, a quarter
+        # of a batch's submission); past its end each batch gets its own
+        # buffer.  Outputs stay valid for the executor's lifetime either way.
+        self.arena = (torch.empty(out_arena_bytes, dtype=torch.uint8, device=self.dev)
+                      if out_arena_bytes else None)
+        self.arena_used = 0
 
     def free_slots(self):
         return sum(not s["busy"] for s in self.slots)
@@ -399,12 +406,21 @@ class GpuExecutor:
             hb.numpy()[:] = segs.view(np.uint8)
             db = slot["segs_d"][:n * am.SEGMENT_BYTES]
             db.copy_(hb, non_blocking=True)
-            out = torch.empty(max(total, 16), dtype=torch.uint8, device=self.dev)
+            out = self._out_buffer(max(total, 16))
             am.ctr_xcrypt_batched(db, self.table, self.pool, out, slot["ws"], self.tune)
             ev = torch.cuda.Event()
             ev.record(s)
         return {"slot": slot, "event": ev, "out": out, "out_off": out_off, "size": size,
                 "fills": [f[0] for f in fills]}
+
+    def _out_buffer(self, nbytes):
+        if self.arena is not None:
+            lo = self.arena_used
+            hi = lo + (nbytes + 255) // 256 * 256
+            if hi <= self.arena.numel():
+                self.arena_used = hi
+                return self.arena[lo:lo + nbytes]
+        return self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.dev)
 
     def done(self, h):
         return h["event"].query()

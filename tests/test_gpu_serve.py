@@ -26,7 +26,10 @@ def test_served_equals_alone(oracle):
     pool_h = np.frombuffer(g.bytes(pool_bytes), np.uint8).copy()
     pool = torch.from_numpy(pool_h).to(DEV)
     nslots = 16
-    ex = serve.GpuExecutor(pool, rs.keys, nslots, nstreams=2, max_segs=1024)
+    # an output arena smaller than the run's output: the first batches are
+    # carved from it, the later ones get buffers of their own
+    ex = serve.GpuExecutor(pool, rs.keys, nslots, nstreams=2, max_segs=1024,
+                           out_arena_bytes=8 << 20)
     kc = serve.KeyCache(nslots, len(rs.keys))
     srv = serve.Server(ex, kc, hbm_budget=48 << 20, max_batch_reqs=1024)
     st, res = srv.run(reqs)
@@ -34,6 +37,7 @@ def test_served_equals_alone(oracle):
     assert st.completed == nreq and st.rejected == 0
     assert st.key_misses > 0 and st.key_hits > 0 and np.all(kc.pins == 0)
     assert st.max_held <= 48 << 20
+    assert 0 < ex.arena_used <= 8 << 20 and int(reqs.size.sum()) > 8 << 20
     for i in range(nreq):
         a, n = int(reqs.in_off[i]), int(reqs.size[i])
         ks = am.key_schedule(rs.keys[reqs.key_id[i]], DEV)
