@@ -28,6 +28,7 @@ GPU.
 """
 from __future__ import annotations
 
+import ctypes
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -334,9 +335,26 @@ class GpuExecutor:
                 "ws": workspace(max_segs, self.dev),
                 "segs_h": torch.empty(max_segs * sb, dtype=torch.uint8, pin_memory=True),
                 "segs_d": torch.empty(max_segs * sb, dtype=torch.uint8, device=self.dev),
-                "keys_h": torch.empty(max_segs * 40, dtype=torch.uint8, pin_memory=True),
-                "keys_d": torch.empty(max_segs * 40, dtype=torch.uint8, device=self.dev),
+                "keys_h": torch.empty(max_segs * 40 + 8, dtype=torch.uint8, pin_memory=True),
+                "keys_d": torch.empty(max_segs * 40 + 8, dtype=torch.uint8, device=self.dev),
+                "sched_d": torch.empty((max_segs, aesmi.SCHEDULE_BYTES), dtype=torch.uint8,
+                                       device=self.dev),
                 "busy": False})
+        # The buffers above are checked once here; each batch then calls the
+        # library directly with their pointers (the checked Python wrappers
+        # cost tens of microseconds of host time per batch).
+        for t, name in ((pool, "pool"), (self.table, "key table")):
+            aesmi._dev_u8(t, name)
+        self.lib = aesmi.lib()
+        self.table_ptr = ctypes.c_void_p(self.table.data_ptr())
+        self.pool_ptr = ctypes.c_void_p(pool.data_ptr())
+        tn = aesmi._tune(tune)
+        self.tune_ref = ctypes.byref(tn) if tn else None
+        self._tune_keep = tn
+        for sl in self.slots:
+            sl["stream_ptr"] = ctypes.c_void_p(sl["stream"].cuda_stream)
+            sl["ws_ptr"] = ctypes.c_void_p(sl["ws"].data_ptr())
+            sl["segs_ptr"] = ctypes.c_void_p(sl["segs_d"].data_ptr())
         # key slot -> (stream slot, event) of an in-flight batch that filled it
         self.filled_by = {}
         # Batch outputs are carved from one preallocated arena while it lasts
@@ -358,20 +376,29 @@ class GpuExecutor:
         kid = np.array([f[1] for f in fills], np.int64)
         order = np.argsort(self.key_len[kid], kind="stable")
         sl, kid = sl[order], kid[order]
-        # staging: n x 32 key bytes, then n int64 slot indices
-        raw = slot["keys_h"][:n * 40].numpy()
-        raw[:n * 32] = self.key_pad[kid].reshape(-1)
-        raw[n * 32:n * 40] = sl.astype("<i8").view(np.uint8)
-        dev = slot["keys_d"][:n * 40]
-        dev.copy_(slot["keys_h"][:n * 40], non_blocking=True)
-        kbytes = dev[:n * 32].view(n, 32)
-        idx = dev[n * 32:n * 40].view(torch.int64)
         lens = self.key_len[kid]
+        # staging: the keys of each length packed back to back, then the n
+        # int64 cache slots (8-byte aligned), in one host-to-device copy
+        raw = slot["keys_h"].numpy()
+        groups, pos = [], 0
         for kb in (16, 24, 32):
-            lo, hi = np.searchsorted(lens, kb), np.searchsorted(lens, kb, "right")
+            lo, hi = int(np.searchsorted(lens, kb)), int(np.searchsorted(lens, kb, "right"))
             if hi > lo:
-                exp = am.expand_keys_device(kbytes[lo:hi, :kb].contiguous())
-                self.table.index_copy_(0, idx[lo:hi], exp)
+                raw[pos:pos + (hi - lo) * kb] = self.key_pad[kid[lo:hi], :kb].reshape(-1)
+                groups.append((kb, lo, hi, pos))
+                pos += (hi - lo) * kb
+        ipos = (pos + 7) // 8 * 8
+        raw[ipos:ipos + 8 * n] = sl.astype("<i8").view(np.uint8)
+        slot["keys_d"][:ipos + 8 * n].copy_(slot["keys_h"][:ipos + 8 * n], non_blocking=True)
+        kbase = slot["keys_d"].data_ptr()
+        sched = slot["sched_d"]
+        for kb, lo, hi, p in groups:
+            am._check(self.lib.aes_expand_keys_device(
+                ctypes.c_void_p(kbase + p), kb, hi - lo,
+                ctypes.c_void_p(sched[lo:hi].data_ptr()), slot["stream_ptr"]),
+                "aes_expand_keys_device")
+        idx = slot["keys_d"][ipos:ipos + 8 * n].view(torch.int64)
+        self.table.index_copy_(0, idx, sched[:n])
 
     def submit(self, reqs, first, last, key_slots, fills):
         torch, am = self.torch, self.am
@@ -407,7 +434,10 @@ class GpuExecutor:
             db = slot["segs_d"][:n * am.SEGMENT_BYTES]
             db.copy_(hb, non_blocking=True)
             out = self._out_buffer(max(total, 16))
-            am.ctr_xcrypt_batched(db, self.table, self.pool, out, slot["ws"], self.tune)
+            am._check(self.lib.aes_ctr_xcrypt_batched(
+                slot["segs_ptr"], n, self.table_ptr, self.table.shape[0], self.pool_ptr,
+                ctypes.c_void_p(out.data_ptr()), self.tune_ref, slot["ws_ptr"],
+                slot["ws"].numel(), slot["stream_ptr"]), "aes_ctr_xcrypt_batched")
             ev = torch.cuda.Event()
             ev.record(s)
         return {"slot": slot, "event": ev, "out": out, "out_off": out_off, "size": size,
