@@ -106,7 +106,7 @@ class KeyCache:
         self.last_use[slots] = self.tick
         self.pins[slots] += 1
         per_req = self.slot_of[key_ids]
-        nmiss_req = int(np.isin(key_ids, missing).sum())
+        nmiss_req = int(np.isin(key_ids, missing).sum()) if missing.size else 0
         self.misses += nmiss_req
         self.hits += int(key_ids.size) - nmiss_req
         fills = list(zip(self.slot_of[missing].tolist(), missing.tolist()))
