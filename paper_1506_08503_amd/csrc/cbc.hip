@@ -5,8 +5,10 @@
 // ciphertext block of the same row (the row's IV for block 0), and deciphering
 // adds the previous ciphertext block after the inverse cipher.
 //   * Encryption is serial along a row and parallel across rows: one lane
-//     per row, two rows per lane interleaved for instruction-level
-//     parallelism, the chaining value kept in registers.
+//     per row, the chaining value kept in registers.  (Two rows per lane,
+//     interleaved for instruction-level parallelism, was measured slower at
+//     every row count: 1.8x slower for 128 to 8192 rows, where the chain
+//     latency decides, and 1-8% slower from 2^18 rows up.)
 //   * Decryption has no serial dependence (every ciphertext block is known):
 //     one lane per block, like ECB, plus one extra 16-byte load of the
 //     previous ciphertext block (or the IV).
@@ -19,7 +21,7 @@
 namespace aesmi {
 namespace {
 
-constexpr int kRowsPerLane = 2;
+constexpr int kRowsPerLane = 1;
 
 template <int NR, int MPL>
 __device__ void cbc_enc_body(const uint32_t *__restrict__ rk, const u32x4 *__restrict__ in,
@@ -166,7 +168,7 @@ hipError_t cbc(bool decrypt, const aes_key_schedule_t *ks, const void *iv, uint3
         hipLaunchKernelGGL(cbc_dec_kernel, dim3(grid), dim3(wg), 0, stream, ks, src, dst, ivp,
                            iv_step, nmsg, nblk);
     } else {
-        // one lane per row (two rows per lane): spread rows over the CUs first
+        // one lane per row: spread rows over the CUs first
         uint32_t wg = 1024;
         const uint64_t lanes = (nmsg + kRowsPerLane - 1) / kRowsPerLane;
         while (wg > 64 && (lanes + wg - 1) / wg < (uint64_t)cu)
