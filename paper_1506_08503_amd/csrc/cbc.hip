@@ -4,11 +4,13 @@
 // at once: block i of a row is enciphered after adding the previous
 // ciphertext block of the same row (the row's IV for block 0), and deciphering
 // adds the previous ciphertext block after the inverse cipher.
-//   * Encryption is serial along a row and parallel across rows: one lane
-//     per row, the chaining value kept in registers.  (Two rows per lane,
-//     interleaved for instruction-level parallelism, was measured slower at
-//     every row count: 1.8x slower for 128 to 8192 rows, where the chain
-//     latency decides, and 1-8% slower from 2^18 rows up.)
+//   * Encryption is serial along a row and parallel across rows, the
+//     chaining value kept in registers: up to 65,536 rows a quad of four
+//     lanes per row (one state column each, ShiftRows through DPP quad
+//     permutations), above that one lane per row.  With few rows the chain
+//     latency decides and the quad roughly halves it; two rows interleaved
+//     per lane, for instruction-level parallelism, was slower at every row
+//     count.
 //   * Decryption has no serial dependence (every ciphertext block is known):
 //     one lane per block, like ECB, plus one extra 16-byte load of the
 //     previous ciphertext block (or the IV).
@@ -22,6 +24,8 @@ namespace aesmi {
 namespace {
 
 constexpr int kRowsPerLane = 1;
+// Up to this many rows the encryption runs four lanes per row.
+constexpr uint64_t kQuadRowsMax = 65536;
 
 template <int NR, int MPL>
 __device__ void cbc_enc_body(const uint32_t *__restrict__ rk, const u32x4 *__restrict__ in,
@@ -97,6 +101,79 @@ __global__ __launch_bounds__(1024) void cbc_enc_kernel(const aes_key_schedule_t 
     }
 }
 
+// Few rows: four lanes per row, lane c of a quad holding state column c, so
+// a chained block costs each lane four table reads per round instead of
+// sixteen and the chain latency drops.  A round's column c reads byte r of
+// column c + r (ShiftRows); the three other columns come from the quad's
+// other lanes by DPP quad permutations.  Quads past the last row are idle
+// as a whole, so every DPP source lane is active.
+constexpr uint32_t kQuadRot1 = 0x39;   // lane c <- lane c + 1 (mod 4)
+constexpr uint32_t kQuadRot2 = 0x4E;   // lane c <- lane c + 2
+constexpr uint32_t kQuadRot3 = 0x93;   // lane c <- lane c + 3
+
+template <uint32_t CTRL>
+__device__ __forceinline__ uint32_t quad_rot(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+template <int NR>
+__device__ void cbc_enc_quad_body(const uint32_t *__restrict__ rk, const uint32_t *__restrict__ in,
+                                  uint32_t *__restrict__ out, const uint32_t *__restrict__ iv,
+                                  uint32_t iv_step, uint64_t nmsg, uint64_t nblk,
+                                  const char *lds, const Lc &lc)
+{
+    const uint32_t c = threadIdx.x & 3u;
+    uint32_t k[NR + 1];
+#pragma unroll
+    for (int r = 0; r <= NR; ++r)
+        k[r] = rk[4 * r + c];
+    const uint64_t nquads = ((uint64_t)gridDim.x * blockDim.x) >> 2;
+    for (uint64_t row = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2; row < nmsg;
+         row += nquads) {
+        uint32_t chain = iv[row * iv_step * 4 + c];
+        const uint32_t *src = in + row * nblk * 4 + c;
+        uint32_t *dst = out + row * nblk * 4 + c;
+        uint32_t next = src[0];
+        for (uint64_t b = 0; b < nblk; ++b) {
+            uint32_t s = next ^ chain ^ k[0];
+            if (b + 1 < nblk)
+                next = src[4 * (b + 1)];
+#pragma unroll
+            for (int r = 1; r < NR; ++r) {
+                const uint32_t s1 = quad_rot<kQuadRot1>(s), s2 = quad_rot<kQuadRot2>(s),
+                               s3 = quad_rot<kQuadRot3>(s);
+                s = col5(TL(0, s, 0), TL(1, s1, 1), TL(2, s2, 2), TL(3, s3, 3), k[r]);
+            }
+            const uint32_t s1 = quad_rot<kQuadRot1>(s), s2 = quad_rot<kQuadRot2>(s),
+                           s3 = quad_rot<kQuadRot3>(s);
+            s = enc_last_col(s, s1, s2, s3, k[NR], lds, lc);
+            chain = s;
+            dst[4 * b] = s;
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void cbc_enc_quad_kernel(const aes_key_schedule_t *__restrict__ ks,
+                                                           const uint32_t *__restrict__ in,
+                                                           uint32_t *__restrict__ out,
+                                                           const uint32_t *__restrict__ iv,
+                                                           uint32_t iv_step, uint64_t nmsg,
+                                                           uint64_t nblk)
+{
+    __shared__ __attribute__((aligned(16))) char lds[kEncLdsBytes];
+    fill_tables(lds, false);
+    __syncthreads();
+    const Lc lc = make_lc(threadIdx.x & 63u);
+    const uint32_t *rk = ks->rk_enc;
+    switch (ks->nr) {
+    case 10: cbc_enc_quad_body<10>(rk, in, out, iv, iv_step, nmsg, nblk, lds, lc); break;
+    case 12: cbc_enc_quad_body<12>(rk, in, out, iv, iv_step, nmsg, nblk, lds, lc); break;
+    case 14: cbc_enc_quad_body<14>(rk, in, out, iv, iv_step, nmsg, nblk, lds, lc); break;
+    default: break;
+    }
+}
+
 // Block g = row * nblk + b.  Each thread walks g = g0 + k * T; the row and the
 // position in the row are advanced incrementally (one division per thread).
 template <int NR>
@@ -167,6 +244,19 @@ hipError_t cbc(bool decrypt, const aes_key_schedule_t *ks, const void *iv, uint3
         const uint32_t grid = (uint32_t)(need < (uint64_t)cu ? need : (uint64_t)cu);
         hipLaunchKernelGGL(cbc_dec_kernel, dim3(grid), dim3(wg), 0, stream, ks, src, dst, ivp,
                            iv_step, nmsg, nblk);
+    } else if (nmsg <= kQuadRowsMax) {
+        // four lanes per row; workgroups of 256 threads (one wave per SIMD),
+        // wider when the rows would need more workgroups than CUs: one
+        // workgroup fits on a CU next to the tables, and up to kQuadRowsMax
+        // rows every row runs at once
+        uint32_t wg = 256;
+        while (wg < 1024 && 4 * nmsg > (uint64_t)wg * cu)
+            wg <<= 1;
+        const uint64_t need = (4 * nmsg + wg - 1) / wg;
+        const uint32_t grid = (uint32_t)(need < (uint64_t)cu ? need : (uint64_t)cu);
+        hipLaunchKernelGGL(cbc_enc_quad_kernel, dim3(grid), dim3(wg), 0, stream, ks,
+                           static_cast<const uint32_t *>(in), static_cast<uint32_t *>(out),
+                           static_cast<const uint32_t *>(iv), iv_step, nmsg, nblk);
     } else {
         // one lane per row: spread rows over the CUs first
         uint32_t wg = 1024;

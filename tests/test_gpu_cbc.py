@@ -106,3 +106,30 @@ def test_cbc_million_rows(oracle, nmsg, msg_bytes):
         assert np.array_equal(dec[r], oracle.cbc_decrypt(key, ivs[r].tobytes(), cr[r])), r
     back = am.cbc_decrypt(ks, iv, ct_d, nmsg)
     assert torch.equal(back, x)
+
+
+@pytest.mark.parametrize("nmsg", [65536, 65537])
+def test_cbc_encrypt_quad_threshold(oracle, nmsg):
+    """Encryption runs four lanes per row up to 65,536 rows and one lane per
+    row above: both sides of the switch, sampled rows against the oracle
+    (first, last, workgroup and grid borders) and the round trip of every row."""
+    msg_bytes = 48
+    g = _rng(nmsg)
+    key = g.bytes(24)
+    ks = am.key_schedule(key)
+    pt = np.frombuffer(g.bytes(nmsg * msg_bytes), np.uint8).reshape(nmsg, msg_bytes)
+    ivs = np.frombuffer(g.bytes(16 * nmsg), np.uint8).reshape(nmsg, 16)
+    x = torch.from_numpy(pt.copy()).to(DEV).view(-1)
+    iv = torch.from_numpy(ivs.copy()).to(DEV).view(-1)
+    ct_d = am.cbc_encrypt(ks, iv, x, nmsg)
+    ct = ct_d.cpu().numpy().reshape(nmsg, msg_bytes)
+    rows = set(range(0, 40)) | set(range(nmsg - 40, nmsg))
+    for b in (16, 64, 256, 1024, 4096, 16384):
+        for k in range(1, 5):
+            for d in (-1, 0, 1):
+                if 0 <= k * b + d < nmsg:
+                    rows.add(k * b + d)
+    rows |= set(int(r) for r in g.integers(0, nmsg, 300))
+    for r in sorted(rows):
+        assert np.array_equal(ct[r], oracle.cbc_encrypt(key, ivs[r].tobytes(), pt[r])), r
+    assert torch.equal(am.cbc_decrypt(ks, iv, ct_d, nmsg), x)
