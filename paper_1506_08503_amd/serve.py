@@ -84,17 +84,67 @@ class KeyCache:
         """Slots for a batch's keys.  Returns (slot per request, distinct slots,
         [(slot, key_id) to fill]) or None when too few slots are unpinned."""
         uniq = np.unique(key_ids)
-        have = self.slot_of[uniq] >= 0
+        slot_u = self.slot_of[uniq]
+        have = slot_u >= 0
+        nmiss = int((~have).sum())
+        if nmiss:
+            # unpinned slots that do not hold a key this batch hits
+            free = self.pins == 0
+            free[slot_u[have]] = False
+            if int(free.sum()) < nmiss:
+                return None
+        return self._acquire_unique(key_ids, uniq, slot_u)
+
+    def max_prefix(self, key_ids: np.ndarray) -> int:
+        """Largest k such that acquire(key_ids[:k]) can succeed: the missing
+        keys of the prefix must fit into the unpinned slots that do not hold a
+        key the prefix hits."""
+        if key_ids.size == 0:
+            return 0
+        _, first = np.unique(key_ids, return_index=True)
+        new = np.zeros(key_ids.size, np.int64)
+        new[first] = 1
+        slot = self.slot_of[key_ids]
+        miss = new * (slot < 0)
+        hit_free = new * ((slot >= 0) & (self.pins[np.maximum(slot, 0)] == 0))
+        need = np.cumsum(miss + hit_free)
+        return int(np.searchsorted(need, int((self.pins == 0).sum()), "right"))
+
+    def take(self, key_ids: np.ndarray):
+        """max_prefix and acquire in one pass (one sort of the keys): returns
+        (k, acquire(key_ids[:k])), k = 0 with None when not even the first
+        request fits."""
+        if key_ids.size == 0:
+            return 0, None
+        uniq, first = np.unique(key_ids, return_index=True)
+        slot_u = self.slot_of[uniq]
+        # a distinct key takes an unpinned slot if it misses, or if it hits a
+        # slot nobody has pinned (it is pinned now); in order of first use
+        needs = (slot_u < 0) | (self.pins[np.maximum(slot_u, 0)] == 0)
+        order = np.argsort(first, kind="stable")
+        cum = np.cumsum(needs[order])
+        m = int(np.searchsorted(cum, int((self.pins == 0).sum()), "right"))
+        if m == 0:
+            return 0, None
+        if m == uniq.size:
+            k = int(key_ids.size)
+        else:
+            k = int(first[order[m]])
+            keep = first < k
+            uniq, slot_u = uniq[keep], slot_u[keep]
+        return k, self._acquire_unique(key_ids[:k], uniq, slot_u)
+
+    def _acquire_unique(self, key_ids, uniq, slot_u):
+        """acquire() given the distinct keys and their current slots: misses
+        take empty slots first, then the least recently used unpinned ones."""
+        have = slot_u >= 0
         missing = uniq[~have]
         if missing.size:
             candidates = np.nonzero(self.pins == 0)[0]
-            # keep slots this batch already hits
             keep = np.zeros(self.nslots, bool)
-            keep[self.slot_of[uniq[have]]] = True
+            keep[slot_u[have]] = True
             candidates = candidates[~keep[candidates]]
-            if candidates.size < missing.size:
-                return None
-            # empty slots first, then least recently used
+            assert candidates.size >= missing.size
             order = np.lexsort((self.last_use[candidates], self.key_of[candidates] >= 0))
             victims = candidates[order[:missing.size]]
             old = self.key_of[victims]
@@ -111,21 +161,6 @@ class KeyCache:
         self.hits += int(key_ids.size) - nmiss_req
         fills = list(zip(self.slot_of[missing].tolist(), missing.tolist()))
         return per_req, slots, fills
-
-    def max_prefix(self, key_ids: np.ndarray) -> int:
-        """Largest k such that acquire(key_ids[:k]) can succeed: the missing
-        keys of the prefix must fit into the unpinned slots that do not hold a
-        key the prefix hits."""
-        if key_ids.size == 0:
-            return 0
-        _, first = np.unique(key_ids, return_index=True)
-        new = np.zeros(key_ids.size, np.int64)
-        new[first] = 1
-        slot = self.slot_of[key_ids]
-        miss = new * (slot < 0)
-        hit_free = new * ((slot >= 0) & (self.pins[np.maximum(slot, 0)] == 0))
-        need = np.cumsum(miss + hit_free)
-        return int(np.searchsorted(need, int((self.pins == 0).sum()), "right"))
 
     def release(self, slots: np.ndarray):
         self.pins[slots] -= 1
@@ -286,12 +321,11 @@ class Server:
         k = int(np.searchsorted(cum_fp, room, "right"))
         k = min(k, int(np.searchsorted(cum_b, self.max_batch_bytes, "right")) or 1,
                 self.max_batch_reqs, arrived - qh)
-        if k > 0:
-            k = min(k, self.kc.max_prefix(reqs.key_id[qh:qh + k]))
         if k == 0:
             return None
-        got = self.kc.acquire(reqs.key_id[qh:qh + k])
-        assert got is not None
+        k, got = self.kc.take(reqs.key_id[qh:qh + k])
+        if k == 0:
+            return None
         per_req, slots, fills = got
         b = Batch(first=qh, last=qh + k, nbytes=int(cum_b[k - 1]), held=int(cum_fp[k - 1]),
                   slots=slots)
@@ -352,6 +386,11 @@ class GpuExecutor:
         self.tune_ref = ctypes.byref(tn) if tn else None
         self._tune_keep = tn
         for sl in self.slots:
+            # one batch per slot at a time: its events and staging are reused
+            # once the batch has been released
+            sl["ev"] = torch.cuda.Event()
+            sl["kev"] = torch.cuda.Event()
+            sl["segs_tab"] = sl["segs_h"].numpy().view(aesmi.segment_dtype())
             sl["stream_ptr"] = ctypes.c_void_p(sl["stream"].cuda_stream)
             sl["ws_ptr"] = ctypes.c_void_p(sl["ws"].data_ptr())
             sl["segs_ptr"] = ctypes.c_void_p(sl["segs_d"].data_ptr())
@@ -402,7 +441,6 @@ class GpuExecutor:
 
     def submit(self, reqs, first, last, key_slots, fills):
         torch, am = self.torch, self.am
-        from .batch import segment_table
         slot = next(s for s in self.slots if not s["busy"])
         n = last - first
         if n > self.max_segs:
@@ -413,35 +451,38 @@ class GpuExecutor:
         out_off = np.zeros(n, np.int64)
         np.cumsum(pad[:-1], out=out_off[1:])
         total = int(pad.sum())
-        segs = segment_table(reqs.in_off[first:last], out_off, size, key_slots.astype(np.uint32),
-                             reqs.ctr0[first:last], reqs.nonce[first:last])
+        # the segment table is written straight into the pinned staging
+        tab = slot["segs_tab"][:n]
+        tab["in_off"] = reqs.in_off[first:last]
+        tab["out_off"] = out_off
+        tab["nbytes"] = size
+        tab["key_slot"] = key_slots
+        tab["ctr0"] = reqs.ctr0[first:last]
+        tab["nonce"] = reqs.nonce[first:last]
         s = slot["stream"]
         with torch.cuda.stream(s):
+            out = self._out_buffer(max(total, 16))
             # schedules another stream's in-flight batch is still writing
             if self.filled_by:
-                for ks in np.unique(key_slots).tolist():
-                    fb = self.filled_by.get(ks)
-                    if fb is not None and fb[0] is not slot:
+                used = np.zeros(self.table.shape[0], bool)
+                used[key_slots] = True
+                for ks, fb in self.filled_by.items():
+                    if fb[0] is not slot and used[ks]:
                         s.wait_event(fb[1])
             if fills:
                 self._fill_keys(slot, fills)
-                kev = torch.cuda.Event()
-                kev.record(s)
+                slot["kev"].record(s)
                 for sl, _ in fills:
-                    self.filled_by[sl] = (slot, kev)
-            hb = slot["segs_h"][:n * am.SEGMENT_BYTES]
-            hb.numpy()[:] = segs.view(np.uint8)
+                    self.filled_by[sl] = (slot, slot["kev"])
             db = slot["segs_d"][:n * am.SEGMENT_BYTES]
-            db.copy_(hb, non_blocking=True)
-            out = self._out_buffer(max(total, 16))
+            db.copy_(slot["segs_h"][:n * am.SEGMENT_BYTES], non_blocking=True)
             am._check(self.lib.aes_ctr_xcrypt_batched(
                 slot["segs_ptr"], n, self.table_ptr, self.table.shape[0], self.pool_ptr,
                 ctypes.c_void_p(out.data_ptr()), self.tune_ref, slot["ws_ptr"],
                 slot["ws"].numel(), slot["stream_ptr"]), "aes_ctr_xcrypt_batched")
-            ev = torch.cuda.Event()
-            ev.record(s)
-        return {"slot": slot, "event": ev, "out": out, "out_off": out_off, "size": size,
-                "fills": [f[0] for f in fills]}
+            slot["ev"].record(s)
+        return {"slot": slot, "event": slot["ev"], "out": out, "out_off": out_off,
+                "size": size, "fills": [f[0] for f in fills]}
 
     def _out_buffer(self, nbytes):
         if self.arena is not None:

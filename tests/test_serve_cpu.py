@@ -200,3 +200,31 @@ def test_summary_skips_warmup():
     assert s_late["max_ms"] == pytest.approx(2.0) and s_late["p50_ms"] == pytest.approx(1.0)
     assert s_late["requests"] == s_all["requests"] == 6
     assert s_late["GBps"] == s_all["GBps"]
+
+
+def test_key_cache_take_equals_max_prefix_then_acquire():
+    """take() is max_prefix() followed by acquire() of that prefix: same
+    prefix length, same slots and fills, same cache state afterwards."""
+    g = np.random.Generator(np.random.PCG64(12))
+    for trial in range(300):
+        nslots, nkeys = int(g.integers(1, 9)), int(g.integers(1, 25))
+        a, b = serve.KeyCache(nslots, nkeys), serve.KeyCache(nslots, nkeys)
+        held = []
+        for step in range(int(g.integers(1, 8))):
+            ids = g.integers(0, nkeys, size=int(g.integers(0, 14)))
+            k_ref = a.max_prefix(ids)
+            ref = a.acquire(ids[:k_ref]) if k_ref else None
+            k, got = b.take(ids)
+            assert k == k_ref, (trial, step)
+            if k:
+                for x, y in zip(ref[:2], got[:2]):
+                    assert np.array_equal(x, y), (trial, step)
+                assert ref[2] == got[2]
+                held.append(ref[1])
+            for name in ("slot_of", "key_of", "last_use", "pins"):
+                assert np.array_equal(getattr(a, name), getattr(b, name)), (trial, step, name)
+            assert (a.tick, a.hits, a.misses) == (b.tick, b.hits, b.misses)
+            if held and g.random() < 0.5:
+                sl = held.pop(int(g.integers(0, len(held))))
+                a.release(sl)
+                b.release(sl)
