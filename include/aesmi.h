@@ -14,7 +14,8 @@
  *  - Plain C types only.  Device buffers are raw device pointers; `stream` is
  *    a hipStream_t passed as void* (NULL = the null stream).
  *  - The caller owns every buffer.  No entry point allocates device memory,
- *    except that aes_batched_graph_create builds a HIP graph (set-up code).
+ *    except that aes_batched_graph_create builds a HIP graph (set-up code)
+ *    and aes_serve_run sets up its key cache and staging for a whole run.
  *  - Launching entry points are stream-ordered and asynchronous: AES_OK means
  *    the arguments passed validation and the work was enqueued on `stream`.
  *    Argument errors are returned before any HIP call is made.
@@ -306,6 +307,83 @@ aes_status_t aes_batched_graph_create(const aes_segment_t *segs_dev, uint32_t ns
                                       aes_batched_graph_t **graph_out);
 aes_status_t aes_batched_graph_launch(aes_batched_graph_t *graph, void *stream);
 aes_status_t aes_batched_graph_destroy(aes_batched_graph_t *graph);
+
+/*
+ * Serving: a continuous-batching request loop on the host that encrypts a
+ * trace of CTR requests on the device (the per-row V and K of sec. II, as
+ * requests arrive).  aes_serve_run plays the whole trace and returns when
+ * every request is done or rejected:
+ *  - requests are admitted in arrival order while the input plus output
+ *    bytes of admitted, unfinished requests fit hbm_budget; a request larger
+ *    than the whole budget is rejected;
+ *  - key schedules live in a device cache of nslots rows (LRU among rows no
+ *    in-flight batch uses); missing keys are expanded on the device into
+ *    their rows on the batch's stream;
+ *  - a batch closes when one of nstreams launch slots is free and nothing
+ *    runs, or the queued bytes reach max_batch_bytes, or the oldest queued
+ *    request has waited window_s, or the whole trace has arrived; it is one
+ *    aes_ctr_xcrypt_batched launch, and batches on different streams overlap;
+ *  - a request's result is the CTR encryption of its payload with its key,
+ *    nonce and ctr0, exactly as aes_ctr_xcrypt would give it alone.
+ */
+typedef struct aes_serve_request {
+    double arrival_s;     /* scheduled arrival, seconds from the start         */
+    uint64_t in_off;      /* payload offset in the input pool (16-aligned)     */
+    uint64_t nbytes;      /* payload length (> 0)                              */
+    uint32_t key_id;      /* index into the key set                            */
+    uint32_t ctr0;        /* first counter value                               */
+    uint8_t  nonce[12];
+    uint32_t reserved;    /* must be 0                                         */
+} aes_serve_request_t;    /* 48 bytes; requests sorted by arrival_s            */
+
+typedef struct aes_serve_params {
+    uint32_t nslots;          /* key-schedule cache rows, >= 1                 */
+    uint32_t nstreams;        /* batches in flight, 1 .. 8                     */
+    uint32_t max_batch_reqs;  /* requests per batch, 1 .. 65536                */
+    uint32_t realtime;        /* 1: requests arrive at arrival_s; 0: at once   */
+    uint64_t hbm_budget;      /* admission budget in bytes                     */
+    uint64_t max_batch_bytes; /* payload bytes that close a batch              */
+    double   window_s;        /* longest wait of the oldest queued request     */
+} aes_serve_params_t;
+
+typedef struct aes_serve_stats {
+    uint64_t completed, rejected, batches, bytes;
+    uint64_t key_hits, key_misses;   /* per request                            */
+    uint64_t max_held;               /* peak admitted input + output bytes     */
+    uint32_t max_inflight;
+    uint32_t reserved;
+    double   elapsed_s;
+} aes_serve_stats_t;
+
+/*
+ * aes_serve_run -- play a request trace (see above).
+ *   reqs        host, nreq requests sorted by arrival_s
+ *   keys32      host, nkeys x 32 bytes: key i in its first key_len[i] bytes
+ *   key_len     host, nkeys bytes: 16, 24 or 32
+ *   pool_dev    device input pool of pool_bytes bytes (16-byte aligned)
+ *   out_dev     device output area of out_bytes bytes (16-byte aligned); the
+ *               outputs of all requests are laid out in it in batch order,
+ *               each padded to 16 bytes, and stay there after the call
+ *   latency_s   host out, nreq: completion minus scheduled arrival (seconds;
+ *               +inf for a rejected request)
+ *   out_off     host out, nreq: offset of the request's output in out_dev
+ *               (UINT64_MAX when rejected)
+ *   stats       host out, may be NULL
+ * Every request and parameter is checked before the run starts: AES_ERR_NULL,
+ * AES_ERR_KEYLEN (a key_len not 16/24/32), AES_ERR_ALIGN (pool, output or an
+ * in_off not 16-aligned), AES_ERR_SEGMENT (a payload outside the pool, a
+ * key_id >= nkeys, nbytes == 0, reserved != 0, ctr0 + blocks > 2^32, or
+ * arrivals out of order), AES_ERR_CONFIG (parameters out of range, or out_bytes
+ * smaller than the sum of the padded payloads).  Unlike the other entry
+ * points this one allocates: the device key table and per-stream staging,
+ * streams and events (set up before the clock starts, freed at the end).
+ * Blocks the calling thread for the whole run; uses the current device.
+ */
+aes_status_t aes_serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8_t *keys32,
+                           const uint8_t *key_len, size_t nkeys, const void *pool_dev,
+                           size_t pool_bytes, void *out_dev, size_t out_bytes,
+                           const aes_serve_params_t *params, double *latency_s,
+                           uint64_t *out_off, aes_serve_stats_t *stats);
 
 /* Text for a status code (static storage). */
 const char *aes_status_string(aes_status_t status);

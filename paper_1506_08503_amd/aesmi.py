@@ -64,6 +64,35 @@ class BatchTune(ctypes.Structure):
                 ("grid_per_cu", ctypes.c_uint32), ("tile_blocks", ctypes.c_uint32)]
 
 
+class ServeParams(ctypes.Structure):
+    _fields_ = [("nslots", ctypes.c_uint32), ("nstreams", ctypes.c_uint32),
+                ("max_batch_reqs", ctypes.c_uint32), ("realtime", ctypes.c_uint32),
+                ("hbm_budget", ctypes.c_uint64), ("max_batch_bytes", ctypes.c_uint64),
+                ("window_s", ctypes.c_double)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
+                ("key_hits", ctypes.c_uint64), ("key_misses", ctypes.c_uint64),
+                ("max_held", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("elapsed_s", ctypes.c_double)]
+
+
+SERVE_REQUEST_BYTES = 48
+
+
+def serve_request_dtype():
+    """numpy dtype with the byte layout of aes_serve_request_t (48 bytes)."""
+    import numpy as np
+    dt = np.dtype([("arrival_s", "<f8"), ("in_off", "<u8"), ("nbytes", "<u8"),
+                   ("key_id", "<u4"), ("ctr0", "<u4"), ("nonce", "u1", (12,)),
+                   ("reserved", "<u4")])
+    assert dt.itemsize == SERVE_REQUEST_BYTES
+    return dt
+
+
+assert ctypes.sizeof(ServeParams) == 40 and ctypes.sizeof(ServeStats) == 72
 assert ctypes.sizeof(KeySchedule) == SCHEDULE_BYTES
 assert ctypes.sizeof(Segment) == SEGMENT_BYTES
 
@@ -111,6 +140,8 @@ def lib():
                                           vp, sz, vp, ctypes.POINTER(vp)], st),
             "aes_batched_graph_launch": ([vp, vp], st),
             "aes_batched_graph_destroy": ([vp], st),
+            "aes_serve_run": ([vp, sz, vp, vp, sz, vp, sz, vp, sz, ctypes.POINTER(ServeParams),
+                               vp, vp, ctypes.POINTER(ServeStats)], st),
             "aes_status_string": ([st], ctypes.c_char_p),
             "aes_version": ([], ctypes.c_char_p),
             "aes_device_cu_count": ([], ctypes.c_int),

@@ -21,7 +21,8 @@ LIB = os.path.join(PKG, "libaesmi.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "ttable.hip", "bitslice.hip", "keyexp.hip", "batched.hip", "cbc.hip", "gcm.hip"]
+SOURCES = ["api.hip", "ttable.hip", "bitslice.hip", "keyexp.hip", "batched.hip", "cbc.hip", "gcm.hip",
+           "serve.hip"]
 
 CFLAGS = ["-std=c++17", "-O3", "-fPIC", "--offload-arch=" + ARCH, "-I" + INCLUDE, "-I" + CSRC,
           "-Wall", "-Wno-unused-function",

@@ -443,6 +443,53 @@ aes_status_t aes_batched_graph_destroy(aes_batched_graph_t *graph)
     return (e1 == hipSuccess && e2 == hipSuccess) ? AES_OK : AES_ERR_HIP;
 }
 
+aes_status_t aes_serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8_t *keys32,
+                           const uint8_t *key_len, size_t nkeys, const void *pool_dev,
+                           size_t pool_bytes, void *out_dev, size_t out_bytes,
+                           const aes_serve_params_t *params, double *latency_s,
+                           uint64_t *out_off, aes_serve_stats_t *stats)
+{
+    if (stats)
+        *stats = aes_serve_stats_t{};
+    if (nreq == 0)
+        return AES_OK;
+    if (!reqs || !keys32 || !key_len || !pool_dev || !out_dev || !params || !latency_s ||
+        !out_off)
+        return AES_ERR_NULL;
+    const aes_serve_params_t &pr = *params;
+    if (pr.nslots == 0 || pr.nstreams == 0 || pr.nstreams > kServeMaxStreams ||
+        pr.max_batch_reqs == 0 || pr.max_batch_reqs > kServeMaxBatch || pr.hbm_budget == 0 ||
+        pr.max_batch_bytes == 0 || !(pr.window_s >= 0.0) || pr.window_s > 1e9 ||
+        pr.realtime > 1)
+        return AES_ERR_CONFIG;
+    for (size_t i = 0; i < nkeys; ++i)
+        if (key_len[i] != 16 && key_len[i] != 24 && key_len[i] != 32)
+            return AES_ERR_KEYLEN;
+    if (!aligned16(pool_dev) || !aligned16(out_dev))
+        return AES_ERR_ALIGN;
+    const uintptr_t p0 = reinterpret_cast<uintptr_t>(pool_dev),
+                    o0 = reinterpret_cast<uintptr_t>(out_dev);
+    if (p0 < o0 + out_bytes && o0 < p0 + pool_bytes)
+        return AES_ERR_OVERLAP;
+    uint64_t out_need = 0;
+    for (size_t i = 0; i < nreq; ++i) {
+        const aes_serve_request_t &r = reqs[i];
+        if (r.in_off & 15u)
+            return AES_ERR_ALIGN;
+        const uint64_t nblk = (r.nbytes + 15u) / 16u;
+        if (r.nbytes == 0 || r.key_id >= nkeys || r.reserved != 0 ||
+            r.in_off > pool_bytes || r.nbytes > pool_bytes - r.in_off ||
+            (uint64_t)r.ctr0 + nblk > (1ull << 32) || !(r.arrival_s >= 0.0) ||
+            !(r.arrival_s < 1e18) || (i && r.arrival_s < reqs[i - 1].arrival_s))
+            return AES_ERR_SEGMENT;
+        out_need += nblk * 16u;
+    }
+    if (out_need > out_bytes)
+        return AES_ERR_CONFIG;
+    return serve_run(reqs, nreq, keys32, key_len, nkeys, static_cast<const uint8_t *>(pool_dev),
+                     static_cast<uint8_t *>(out_dev), pr, latency_s, out_off, stats);
+}
+
 const char *aes_status_string(aes_status_t status)
 {
     switch (status) {

@@ -51,6 +51,18 @@ hipError_t ghash(const uint32_t h_words[4], const void *x, uint64_t nblocks, voi
 // --- device key expansion (keyexp.hip) -------------------------------------
 hipError_t expand_keys_device(const uint8_t *keys, uint32_t key_bytes, uint64_t nkeys,
                               aes_key_schedule_t *ks, hipStream_t stream);
+// Key i: the first lens[i] bytes of keys32 + 32 i; its schedule -> table[slots[i]].
+hipError_t expand_keys_to_slots(const uint8_t *keys32, const uint8_t *lens,
+                                const uint32_t *slots, uint32_t n, aes_key_schedule_t *table,
+                                hipStream_t stream);
+
+// --- serving loop (serve.hip); arguments checked by aes_serve_run ----------
+constexpr uint32_t kServeMaxStreams = 8;
+constexpr uint32_t kServeMaxBatch = 65536;
+aes_status_t serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8_t *keys32,
+                       const uint8_t *key_len, size_t nkeys, const uint8_t *pool, uint8_t *out,
+                       const aes_serve_params_t &pr, double *latency_s, uint64_t *out_off,
+                       aes_serve_stats_t *stats);
 
 // --- batched persistent kernel (batched.hip) -------------------------------
 size_t batched_workspace_bytes(uint32_t nsegs);

@@ -1,0 +1,366 @@
+// serve.hip -- the continuous-batching request loop behind aes_serve_run.
+//
+// Host code only: it plays a trace of CTR requests (arrival time, payload in
+// a device pool, key id, nonce, first counter) against the device.  Requests
+// are admitted in arrival order under an HBM budget, their key schedules are
+// kept in a device cache (LRU among rows that no in-flight batch uses,
+// misses expanded on the device into their rows), and queued requests are
+// closed into batches, each one aes_ctr_xcrypt_batched launch on one of a few
+// streams, so that batches overlap on the device while the loop keeps
+// admitting.  This is the per-row key and IV form of sec. II applied to
+// requests that arrive over time.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace aesmi {
+namespace {
+
+// Which key sits in which row of the device schedule table.  A row is pinned
+// once per in-flight batch that uses it and is never evicted while pinned.
+struct KeyCache {
+    std::vector<int64_t> slot_of;    // per key: row or -1
+    std::vector<int64_t> key_of;     // per row: key or -1
+    std::vector<uint64_t> last_use;  // per row
+    std::vector<uint32_t> pins;      // per row
+    std::vector<uint64_t> seen;      // per key: stamp of the batch being formed
+    std::vector<uint64_t> missed;    // per key: stamp when it missed in that batch
+    std::vector<uint64_t> hit_row;   // per row: stamp when a key of that batch hit it
+    uint64_t tick = 0, stamp = 0, hits = 0, misses = 0;
+    uint32_t unpinned = 0;
+
+    KeyCache(size_t nkeys, uint32_t nslots)
+        : slot_of(nkeys, -1), key_of(nslots, -1), last_use(nslots, 0), pins(nslots, 0),
+          seen(nkeys, 0), missed(nkeys, 0), hit_row(nslots, 0), unpinned(nslots)
+    {
+    }
+
+    // Largest k <= kmax such that the distinct keys of requests [0, k) fit:
+    // every key that misses, and every key that hits an unpinned row, needs
+    // one of the unpinned rows.  Then pins (and fills) the rows of that
+    // prefix.  Returns k (0: not even the first request fits now); `keys`
+    // gets the prefix's distinct keys, `fills` the (row, key) pairs to expand.
+    uint32_t take(const uint32_t *key_id, uint32_t kmax, std::vector<uint32_t> &keys,
+                  std::vector<std::pair<uint32_t, uint32_t>> &fills)
+    {
+        ++stamp;
+        keys.clear();
+        fills.clear();
+        uint32_t need = 0, k = 0;
+        for (; k < kmax; ++k) {
+            const uint32_t key = key_id[k];
+            if (seen[key] == stamp)
+                continue;
+            const int64_t row = slot_of[key];
+            const bool takes = row < 0 || pins[row] == 0;
+            if (takes && need + 1 > unpinned)
+                break;
+            seen[key] = stamp;
+            need += takes;
+            keys.push_back(key);
+        }
+        if (k == 0)
+            return 0;
+        // rows this batch hits are not eviction candidates
+        uint32_t nmiss = 0;
+        for (uint32_t key : keys) {
+            if (slot_of[key] >= 0)
+                hit_row[slot_of[key]] = stamp;
+            else
+                ++nmiss;
+        }
+        if (nmiss) {
+            std::vector<uint32_t> cand;
+            for (uint32_t r = 0; r < key_of.size(); ++r)
+                if (pins[r] == 0 && hit_row[r] != stamp)
+                    cand.push_back(r);
+            // empty rows first, then the least recently used
+            std::partial_sort(cand.begin(), cand.begin() + nmiss, cand.end(),
+                              [&](uint32_t a, uint32_t b) {
+                                  const bool fa = key_of[a] >= 0, fb = key_of[b] >= 0;
+                                  if (fa != fb)
+                                      return !fa;
+                                  return last_use[a] < last_use[b];
+                              });
+            uint32_t v = 0;
+            for (uint32_t key : keys) {
+                if (slot_of[key] >= 0)
+                    continue;
+                const uint32_t row = cand[v++];
+                if (key_of[row] >= 0)
+                    slot_of[key_of[row]] = -1;
+                key_of[row] = key;
+                slot_of[key] = row;
+                missed[key] = stamp;
+                fills.emplace_back(row, key);
+            }
+        }
+        ++tick;
+        for (uint32_t key : keys) {
+            const uint32_t row = (uint32_t)slot_of[key];
+            last_use[row] = tick;
+            if (pins[row]++ == 0)
+                --unpinned;
+        }
+        for (uint32_t i = 0; i < k; ++i) {
+            if (missed[key_id[i]] == stamp)
+                ++misses;
+            else
+                ++hits;
+        }
+        return k;
+    }
+
+    void release(const std::vector<uint32_t> &rows)
+    {
+        for (uint32_t row : rows)
+            if (--pins[row] == 0)
+                ++unpinned;
+    }
+};
+
+// Per-stream launch slot: staging for one batch at a time.
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr, filled = nullptr;
+    aes_segment_t *segs_h = nullptr;   // pinned
+    aes_segment_t *segs_d = nullptr;
+    uint8_t *fill_h = nullptr;         // pinned: keys32 | lens | slots
+    uint8_t *fill_d = nullptr;
+    void *ws = nullptr;
+    bool busy = false;
+    // the batch in flight
+    uint64_t first = 0, last = 0, held = 0, bytes = 0;
+    std::vector<uint32_t> rows, filled_rows;
+};
+
+struct Resources {
+    aes_key_schedule_t *table = nullptr;
+    std::vector<Slot> slots;
+    ~Resources()
+    {
+        for (Slot &s : slots) {
+            if (s.stream)
+                (void)hipStreamSynchronize(s.stream);
+        }
+        for (Slot &s : slots) {
+            if (s.done)
+                (void)hipEventDestroy(s.done);
+            if (s.filled)
+                (void)hipEventDestroy(s.filled);
+            if (s.stream)
+                (void)hipStreamDestroy(s.stream);
+            (void)hipHostFree(s.segs_h);
+            (void)hipHostFree(s.fill_h);
+            (void)hipFree(s.segs_d);
+            (void)hipFree(s.fill_d);
+            (void)hipFree(s.ws);
+        }
+        (void)hipFree(table);
+    }
+};
+
+inline uint64_t pad16(uint64_t n) { return (n + 15u) & ~(uint64_t)15u; }
+
+// Bytes of one fill staging area for up to f keys: keys32, lens, 4-aligned rows.
+inline size_t fill_bytes(uint32_t f) { return (size_t)f * 32 + ((f + 3u) & ~3u) + (size_t)f * 4; }
+
+}  // namespace
+
+aes_status_t serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8_t *keys32,
+                       const uint8_t *key_len, size_t nkeys, const uint8_t *pool, uint8_t *out,
+                       const aes_serve_params_t &pr, double *latency_s, uint64_t *out_off,
+                       aes_serve_stats_t *stats)
+{
+    using clock = std::chrono::steady_clock;
+    const uint32_t nstreams = pr.nstreams, maxb = pr.max_batch_reqs;
+    const uint32_t nfill = std::min<uint32_t>(maxb, pr.nslots);
+    // footprint = input + 16-padded output; prefix sums of footprint and bytes
+    std::vector<uint64_t> fp(nreq), cum_fp(nreq + 1, 0), cum_b(nreq + 1, 0);
+    std::vector<uint32_t> key_id(nreq);
+    for (size_t i = 0; i < nreq; ++i) {
+        fp[i] = reqs[i].nbytes + pad16(reqs[i].nbytes);
+        cum_fp[i + 1] = cum_fp[i] + fp[i];
+        cum_b[i + 1] = cum_b[i] + reqs[i].nbytes;
+        key_id[i] = reqs[i].key_id;
+        latency_s[i] = std::numeric_limits<double>::infinity();
+        out_off[i] = UINT64_MAX;
+    }
+
+    Resources res;
+    KeyCache kc(nkeys, pr.nslots);
+    if (hipMalloc(&res.table, sizeof(aes_key_schedule_t) * pr.nslots) != hipSuccess)
+        return AES_ERR_HIP;
+    res.slots.resize(nstreams);
+    for (Slot &s : res.slots) {
+        if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&s.filled, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc((void **)&s.segs_h, sizeof(aes_segment_t) * maxb, 0) != hipSuccess ||
+            hipHostMalloc((void **)&s.fill_h, fill_bytes(nfill), 0) != hipSuccess ||
+            hipMalloc((void **)&s.segs_d, sizeof(aes_segment_t) * maxb) != hipSuccess ||
+            hipMalloc((void **)&s.fill_d, fill_bytes(nfill)) != hipSuccess ||
+            hipMalloc(&s.ws, batched_workspace_bytes(maxb)) != hipSuccess)
+            return AES_ERR_HIP;
+        s.rows.reserve(pr.nslots);
+    }
+    // row -> stream slot whose in-flight batch expanded it (-1: none)
+    std::vector<int32_t> filled_by(pr.nslots, -1);
+    std::vector<uint32_t> keys;
+    std::vector<std::pair<uint32_t, uint32_t>> fills;
+    std::vector<double> complete(nreq, std::numeric_limits<double>::infinity());
+
+    aes_serve_stats_t st{};
+    uint64_t qh = 0, held = 0, arena = 0;
+    uint32_t inflight = 0;
+    const double window = pr.window_s;
+    const auto t0 = clock::now();
+    auto now_s = [&]() { return std::chrono::duration<double>(clock::now() - t0).count(); };
+
+    uint64_t arrived = pr.realtime ? 0 : nreq;
+    while (qh < nreq || inflight) {
+        const double now = now_s();
+        // requests are sorted by arrival time
+        while (arrived < nreq && reqs[arrived].arrival_s <= now)
+            ++arrived;
+        bool progressed = false;
+        // retire finished batches
+        for (uint32_t si = 0; si < nstreams; ++si) {
+            Slot &s = res.slots[si];
+            if (!s.busy)
+                continue;
+            const hipError_t q = hipEventQuery(s.done);
+            if (q == hipErrorNotReady)
+                continue;
+            if (q != hipSuccess)
+                return AES_ERR_HIP;
+            const double tdone = now_s();
+            for (uint64_t i = s.first; i < s.last; ++i)
+                complete[i] = tdone;
+            held -= s.held;
+            kc.release(s.rows);
+            for (uint32_t row : s.filled_rows)
+                if (filled_by[row] == (int32_t)si)
+                    filled_by[row] = -1;
+            st.completed += s.last - s.first;
+            st.bytes += s.bytes;
+            s.busy = false;
+            --inflight;
+            progressed = true;
+        }
+        // reject what can never fit
+        while (qh < arrived && fp[qh] > pr.hbm_budget) {
+            ++st.rejected;
+            ++qh;
+            progressed = true;
+        }
+        if (qh < arrived && inflight < nstreams) {
+            const uint64_t queued = cum_b[arrived] - cum_b[qh];
+            const double oldest = pr.realtime ? now - reqs[qh].arrival_s : 0.0;
+            if (!inflight || queued >= pr.max_batch_bytes || oldest >= window || arrived == nreq) {
+                // largest prefix within the budget, the batch size limits and
+                // the key cache
+                const uint64_t room = pr.hbm_budget - held;
+                uint64_t k = std::upper_bound(cum_fp.begin() + qh + 1, cum_fp.begin() + arrived + 1,
+                                              cum_fp[qh] + room) - (cum_fp.begin() + qh + 1);
+                uint64_t kb = std::upper_bound(cum_b.begin() + qh + 1, cum_b.begin() + arrived + 1,
+                                               cum_b[qh] + pr.max_batch_bytes) -
+                              (cum_b.begin() + qh + 1);
+                k = std::min<uint64_t>({k, std::max<uint64_t>(kb, 1), maxb, arrived - qh});
+                if (k)
+                    k = kc.take(key_id.data() + qh, (uint32_t)k, keys, fills);
+                if (k) {
+                    uint32_t si = 0;
+                    while (res.slots[si].busy)
+                        ++si;
+                    Slot &s = res.slots[si];
+                    // the rows this batch reads that another stream's
+                    // in-flight batch is still expanding
+                    for (uint32_t key : keys) {
+                        const uint32_t row = (uint32_t)kc.slot_of[key];
+                        const int32_t fb = filled_by[row];
+                        if (fb >= 0 && fb != (int32_t)si &&
+                            hipStreamWaitEvent(s.stream, res.slots[fb].filled, 0) != hipSuccess)
+                            return AES_ERR_HIP;
+                    }
+                    s.filled_rows.clear();
+                    if (!fills.empty()) {
+                        const uint32_t f = (uint32_t)fills.size();
+                        uint8_t *kh = s.fill_h, *lh = kh + (size_t)f * 32;
+                        uint32_t *rh = reinterpret_cast<uint32_t *>(lh + ((f + 3u) & ~3u));
+                        for (uint32_t j = 0; j < f; ++j) {
+                            std::memcpy(kh + 32u * j, keys32 + 32u * fills[j].second, 32);
+                            lh[j] = key_len[fills[j].second];
+                            rh[j] = fills[j].first;
+                            filled_by[fills[j].first] = (int32_t)si;
+                            s.filled_rows.push_back(fills[j].first);
+                        }
+                        const size_t fb = fill_bytes(f);
+                        uint8_t *kd = s.fill_d, *ld = kd + (size_t)f * 32;
+                        const uint32_t *rd = reinterpret_cast<const uint32_t *>(ld + ((f + 3u) & ~3u));
+                        if (hipMemcpyAsync(s.fill_d, s.fill_h, fb, hipMemcpyHostToDevice, s.stream) !=
+                                hipSuccess ||
+                            expand_keys_to_slots(kd, ld, rd, f, res.table, s.stream) != hipSuccess ||
+                            hipEventRecord(s.filled, s.stream) != hipSuccess)
+                            return AES_ERR_HIP;
+                    }
+                    uint64_t off = 0;
+                    for (uint64_t j = 0; j < k; ++j) {
+                        const aes_serve_request_t &r = reqs[qh + j];
+                        aes_segment_t &g = s.segs_h[j];
+                        g.in_off = r.in_off;
+                        g.out_off = arena + off;
+                        g.nbytes = r.nbytes;
+                        g.key_slot = (uint32_t)kc.slot_of[r.key_id];
+                        g.ctr0 = r.ctr0;
+                        std::memcpy(g.nonce, r.nonce, 12);
+                        g.reserved = 0;
+                        out_off[qh + j] = arena + off;
+                        off += pad16(r.nbytes);
+                    }
+                    if (hipMemcpyAsync(s.segs_d, s.segs_h, sizeof(aes_segment_t) * k,
+                                       hipMemcpyHostToDevice, s.stream) != hipSuccess ||
+                        batched_ctr(s.segs_d, (uint32_t)k, res.table, pr.nslots, pool, out,
+                                    nullptr, s.ws, s.stream) != hipSuccess ||
+                        hipEventRecord(s.done, s.stream) != hipSuccess)
+                        return AES_ERR_HIP;
+                    arena += off;
+                    s.rows.clear();
+                    for (uint32_t key : keys)
+                        s.rows.push_back((uint32_t)kc.slot_of[key]);
+                    s.first = qh;
+                    s.last = qh + k;
+                    s.held = cum_fp[qh + k] - cum_fp[qh];
+                    s.bytes = cum_b[qh + k] - cum_b[qh];
+                    s.busy = true;
+                    held += s.held;
+                    ++inflight;
+                    ++st.batches;
+                    st.max_inflight = std::max(st.max_inflight, inflight);
+                    st.max_held = std::max(st.max_held, held);
+                    qh += k;
+                    progressed = true;
+                }
+            }
+        }
+        (void)progressed;
+    }
+    st.elapsed_s = now_s();
+    for (size_t i = 0; i < nreq; ++i)
+        if (std::isfinite(complete[i]))
+            latency_s[i] = complete[i] - (pr.realtime ? reqs[i].arrival_s : 0.0);
+    st.key_hits = kc.hits;
+    st.key_misses = kc.misses;
+    if (stats)
+        *stats = st;
+    return AES_OK;
+}
+
+}  // namespace aesmi

@@ -509,3 +509,69 @@ class GpuExecutor:
 
     def idle(self):
         pass
+
+
+# ------------------------------------------------------------- native loop
+class NativeResults:
+    """Outputs of a native run: request i -> a view into the output area
+    (None when rejected)."""
+
+    def __init__(self, out, out_off, size):
+        self.out, self.out_off, self.size = out, out_off, size
+
+    def __len__(self):
+        return int(self.size.size)
+
+    def __getitem__(self, i):
+        o = int(self.out_off[i])
+        if o == np.iinfo(np.uint64).max:
+            return None
+        return self.out[o:o + int(self.size[i])]
+
+
+def run_native(pool, keys: list, reqs: Requests, nslots: int, nstreams: int = 2,
+               hbm_budget: int = 4 << 30, max_batch_reqs: int = 8192,
+               max_batch_bytes: int = 64 << 20, window_s: float = 50e-6,
+               realtime: bool = True, out=None):
+    """The same request loop as Server with GpuExecutor, run in the library
+    (aes_serve_run): admission, the key-schedule cache, batch formation and
+    launches happen in C++ without returning to Python per batch.  Returns
+    (Stats, NativeResults).  `out` (uint8 device tensor) must hold every
+    request's 16-padded output; by default one is allocated."""
+    import torch
+    from . import aesmi
+    aesmi._dev_u8(pool, "pool")
+    n = len(reqs)
+    tab = np.zeros(n, dtype=aesmi.serve_request_dtype())
+    tab["arrival_s"] = reqs.arrival
+    tab["in_off"] = reqs.in_off
+    tab["nbytes"] = reqs.size
+    tab["key_id"] = reqs.key_id
+    tab["ctr0"] = reqs.ctr0
+    tab["nonce"] = reqs.nonce
+    keys32 = np.zeros((len(keys), 32), np.uint8)
+    klen = np.zeros(len(keys), np.uint8)
+    for i, k in enumerate(keys):
+        keys32[i, :len(k)] = np.frombuffer(k, np.uint8)
+        klen[i] = len(k)
+    need = int(((reqs.size + 15) // 16 * 16).sum())
+    if out is None:
+        out = torch.empty(max(need, 16), dtype=torch.uint8, device=pool.device)
+    aesmi._dev_u8(out, "output area")
+    prm = aesmi.ServeParams(nslots, nstreams, max_batch_reqs, 1 if realtime else 0,
+                            hbm_budget, max_batch_bytes, window_s)
+    lat = np.empty(n, np.float64)
+    off = np.empty(n, np.uint64)
+    st = aesmi.ServeStats()
+    with torch.cuda.device(pool.device):
+        torch.cuda.synchronize(pool.device)
+        aesmi._check(aesmi.lib().aes_serve_run(
+            tab.ctypes.data, n, keys32.ctypes.data, klen.ctypes.data, len(keys),
+            pool.data_ptr(), pool.numel(), out.data_ptr(), out.numel(), ctypes.byref(prm),
+            lat.ctypes.data, off.ctypes.data, ctypes.byref(st)), "aes_serve_run")
+    stats = Stats(completed=int(st.completed), rejected=int(st.rejected), bytes=int(st.bytes),
+                  batches=int(st.batches), elapsed_s=float(st.elapsed_s), latency_s=lat,
+                  admission_wait_s=np.zeros(n), key_hits=int(st.key_hits),
+                  key_misses=int(st.key_misses), max_inflight=int(st.max_inflight),
+                  max_held=int(st.max_held))
+    return stats, NativeResults(out, off, reqs.size)

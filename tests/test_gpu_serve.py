@@ -55,3 +55,56 @@ def test_served_equals_alone(oracle):
     assert not bad, bad[:10]
     s = st.summary()
     assert s["p99_ms"] >= s["p50_ms"] > 0
+
+
+@pytest.mark.parametrize("nstreams,realtime", [(2, True), (4, False), (1, True)])
+def test_native_served_equals_alone(oracle, nstreams, realtime):
+    """The request loop run inside the library (aes_serve_run): every request
+    equals the same request run alone and the oracle's CTR; a 16-row key
+    cache for 64 keys forces evictions and refills, several streams force
+    waits on another stream's key expansion, and a 48 MiB budget holds
+    admission back."""
+    nreq, pool_bytes = 3000, 32 << 20
+    rs = wl.serving_inputs(nreq, 3e5, nkeys=64, median=4096, sigma=2.0, max_size=1 << 20,
+                           seed=31 + nstreams)
+    reqs = serve.requests_from_stream(rs, pool_bytes, seed=31)
+    g = np.random.Generator(np.random.PCG64(32))
+    pool_h = np.frombuffer(g.bytes(pool_bytes), np.uint8).copy()
+    pool = torch.from_numpy(pool_h).to(DEV)
+    st, res = serve.run_native(pool, rs.keys, reqs, nslots=16, nstreams=nstreams,
+                               hbm_budget=48 << 20, max_batch_reqs=1024, realtime=realtime)
+    torch.cuda.synchronize()
+    assert st.completed == nreq and st.rejected == 0
+    assert st.key_misses > 0 and st.key_hits > 0 and st.key_hits + st.key_misses == nreq
+    assert st.max_held <= 48 << 20 and 1 <= st.max_inflight <= nstreams
+    assert np.all(np.isfinite(st.latency_s)) and np.all(st.latency_s > 0)
+    got = [res[i].cpu().numpy() for i in range(nreq)]
+    for i in range(nreq):
+        a, n = int(reqs.in_off[i]), int(reqs.size[i])
+        ks = am.key_schedule(rs.keys[reqs.key_id[i]], DEV)
+        alone = am.ctr_xcrypt(ks, reqs.nonce[i].tobytes(), int(reqs.ctr0[i]), pool[a:a + n])
+        assert np.array_equal(got[i], alone.cpu().numpy()), i
+
+    def agrees(i):
+        a, n = int(reqs.in_off[i]), int(reqs.size[i])
+        exp = oracle.ctr_xcrypt(rs.keys[reqs.key_id[i]], reqs.nonce[i].tobytes(),
+                                int(reqs.ctr0[i]), pool_h[a:a + n])
+        return np.array_equal(got[i], exp)
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as pool_ex:
+        bad = [i for i, ok in zip(range(nreq), pool_ex.map(agrees, range(nreq))) if not ok]
+    assert not bad, bad[:10]
+
+
+def test_native_rejects_oversize():
+    """A request larger than the whole budget is rejected (no output, infinite
+    latency); the others are served."""
+    rs = wl.serving_inputs(200, 1e5, nkeys=8, median=4096, sigma=1.0, max_size=1 << 16, seed=5)
+    reqs = serve.requests_from_stream(rs, 8 << 20, seed=5)
+    reqs.size[7] = 6 << 20                                   # 6 MiB in + 6 MiB out > 8 MiB
+    reqs.in_off[7] = 0
+    pool = torch.zeros(8 << 20, dtype=torch.uint8, device=DEV)
+    st, res = serve.run_native(pool, rs.keys, reqs, nslots=8, hbm_budget=8 << 20)
+    torch.cuda.synchronize()
+    assert st.rejected == 1 and st.completed == 199
+    assert res[7] is None and np.isinf(st.latency_s[7])
+    assert res[8] is not None and res[8].numel() == int(reqs.size[8])

@@ -203,3 +203,49 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_serve_run_validation():
+    """aes_serve_run checks every request and parameter before it sets
+    anything up (no GPU is touched for these cases)."""
+    f = L.aes_serve_run
+    dt = am.serve_request_dtype()
+    reqs = np.zeros(3, dtype=dt)
+    reqs["arrival_s"] = [0.0, 1e-6, 2e-6]
+    reqs["in_off"] = [0, 16, 4096]
+    reqs["nbytes"] = [5, 100, 4096]
+    reqs["key_id"] = [0, 1, 0]
+    keys32 = np.zeros((2, 32), np.uint8)
+    klen = np.array([16, 32], np.uint8)
+    lat = np.zeros(3, np.float64)
+    off = np.zeros(3, np.uint64)
+    pool, pool_bytes = VP(0x100000), 1 << 20
+    out, out_bytes = VP(0x400000), 1 << 20
+    prm = am.ServeParams(16, 2, 1024, 1, 1 << 30, 1 << 26, 50e-6)
+
+    def call(r=reqs, k=klen, p=pool, pb=pool_bytes, o=out, ob=out_bytes, pr=prm, n=None):
+        return f(r.ctypes.data, len(r) if n is None else n, keys32.ctypes.data, k.ctypes.data,
+                 len(k), p, pb, o, ob, ctypes.byref(pr), lat.ctypes.data, off.ctypes.data, None)
+    assert call(n=0) == 0
+    assert f(None, 3, keys32.ctypes.data, klen.ctypes.data, 2, pool, pool_bytes, out,
+             out_bytes, ctypes.byref(prm), lat.ctypes.data, off.ctypes.data, None) == -1
+    for bad in (am.ServeParams(0, 2, 1024, 1, 1 << 30, 1 << 26, 50e-6),
+                am.ServeParams(16, 9, 1024, 1, 1 << 30, 1 << 26, 50e-6),
+                am.ServeParams(16, 2, 0, 1, 1 << 30, 1 << 26, 50e-6),
+                am.ServeParams(16, 2, 1024, 1, 0, 1 << 26, 50e-6),
+                am.ServeParams(16, 2, 1024, 1, 1 << 30, 1 << 26, -1.0)):
+        assert call(pr=bad) == -9
+    assert call(k=np.array([16, 20], np.uint8)) == -2
+    assert call(p=VP(0x100008)) == -4
+    assert call(o=VP(0x100000 + 4096)) == -5                 # output inside the pool
+    cases = [("in_off", 1, 8, -4), ("in_off", 2, pool_bytes - 16, -7),
+             ("key_id", 1, 2, -7), ("nbytes", 0, 0, -7), ("reserved", 2, 1, -7),
+             ("arrival_s", 2, 0.0, -7)]
+    for field, i, value, code in cases:
+        r = reqs.copy()
+        r[field][i] = value
+        assert call(r=r) == code, (field, value)
+    r = reqs.copy()
+    r["ctr0"][2] = 2 ** 32 - 10                             # 256 blocks from 2^32 - 10
+    assert call(r=r) == -7
+    assert call(ob=16 + 112 + 4096 - 16) == -9               # one byte block short
