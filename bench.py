@@ -146,29 +146,45 @@ SERVING_WARMUP = 5000
 def serving_leg(nreq):
     """Open-loop Poisson arrivals of AES-128/256 CTR requests (lognormal sizes,
     median 4 KiB, sigma 2, clipped to 16 MiB; 1,024 keys; 4 GiB HBM budget),
-    payloads already in device memory.  Capacity is measured closed-loop, then
-    latency at 50% and 80% of it; key caches of 1,024 and 256 slots.  Each
-    open-loop run serves SERVING_WARMUP requests more than nreq and its latency
-    percentiles cover the last nreq (the run starts with an empty key cache and
-    an idle loop); p99_ms_all is the 99th percentile over every request."""
+    payloads already in device memory, served by the library's request loop
+    (aes_serve_run: admission, key cache, batching and launches in C++, two
+    streams).  Capacity is measured closed-loop, then latency at 50% and 80%
+    of it; key caches of 1,024 and 256 slots.  Each open-loop run serves
+    SERVING_WARMUP requests more than nreq and its latency percentiles cover
+    the last nreq (the run starts with an empty key cache and an idle loop);
+    p99_ms_all is the 99th percentile over every request.  The same loop
+    written in Python (serve.Server) is measured closed-loop beside it."""
     import numpy as np
     import torch
     from paper_1506_08503_amd import serve, workloads as wl
     pool_bytes = 256 << 20
     g = np.random.Generator(np.random.PCG64(wl.SEED_SERVING + 1))
     pool = torch.from_numpy(np.frombuffer(g.bytes(pool_bytes), np.uint8).copy()).cuda()
+    out = [None]
 
-    def run(rate, n, nslots, closed=False):
+    def out_for(reqs):
+        need = int(((reqs.size + 15) // 16 * 16).sum())
+        if out[0] is None or out[0].numel() < need:
+            out[0] = None
+            out[0] = torch.empty(need, dtype=torch.uint8, device="cuda")
+        return out[0]
+
+    def run(rate, n, nslots, closed=False, python_loop=False):
         warm = 0 if closed else SERVING_WARMUP
         rs = wl.serving_inputs(n + warm, rate, nkeys=1024)
         reqs = serve.requests_from_stream(rs, pool_bytes)
         if closed:
             reqs.arrival[:] = 0.0
-        ex = serve.GpuExecutor(pool, rs.keys, nslots, nstreams=2, max_segs=8192,
-                               out_arena_bytes=4 << 30)
-        srv = serve.Server(ex, serve.KeyCache(nslots, len(rs.keys)), hbm_budget=4 << 30,
-                           max_batch_reqs=8192, window_s=50e-6)
-        st, _ = srv.run(reqs)
+        if python_loop:
+            ex = serve.GpuExecutor(pool, rs.keys, nslots, nstreams=2, max_segs=8192,
+                                   out_arena_bytes=4 << 30)
+            srv = serve.Server(ex, serve.KeyCache(nslots, len(rs.keys)), hbm_budget=4 << 30,
+                               max_batch_reqs=8192, window_s=50e-6)
+            st, _ = srv.run(reqs)
+        else:
+            st, _ = serve.run_native(pool, rs.keys, reqs, nslots, nstreams=2,
+                                     hbm_budget=4 << 30, max_batch_reqs=8192,
+                                     window_s=50e-6, out=out_for(reqs))
         torch.cuda.synchronize()
         s = st.summary(skip=warm)
         if warm:
@@ -177,8 +193,9 @@ def serving_leg(nreq):
         return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
 
     run(1e5, 5000, 1024, closed=True)            # warm-up
-    out = {"workload": "%d requests, lognormal sizes median 4 KiB sigma 2 (<=16 MiB), "
-                       "1024 keys (half AES-128, half AES-256), 4 GiB budget" % nreq}
+    res_all = {"workload": "%d requests, lognormal sizes median 4 KiB sigma 2 (<=16 MiB), "
+                           "1024 keys (half AES-128, half AES-256), 4 GiB budget" % nreq,
+               "loop": "aes_serve_run (C++), 2 streams"}
     for nslots in (1024, 256):
         cap = run(1e5, nreq, nslots, closed=True)
         rate = cap["req_per_s"]
@@ -186,8 +203,11 @@ def serving_leg(nreq):
         for rho in (0.5, 0.8):
             res["rho%.1f" % rho] = dict(run(rho * rate, nreq, nslots), offered_req_per_s=
                                         round(rho * rate))
-        out["key_slots_%d" % nslots] = res
-    return out
+        res_all["key_slots_%d" % nslots] = res
+    run(1e5, 5000, 1024, closed=True, python_loop=True)
+    res_all["python_loop_capacity_1024_slots"] = run(1e5, nreq, 1024, closed=True,
+                                                     python_loop=True)["req_per_s"]
+    return res_all
 
 
 def sweep_fig3():

@@ -12,12 +12,14 @@
 //      get no tiles and set the status word to AES_ERR_SEGMENT (a key
 //      schedule without a valid round count is caught by the CTR kernel,
 //      which skips the segment's tiles and sets the same status).
-//   2. persistent CTR kernel (a fixed grid of workgroups per CU): each wave
-//      claims tile t with one atomic add, finds its segment with a 64-way
-//      ballot search over tile_start (three rounds for 10^4 segments), loads
-//      that segment's key schedule and nonce, and runs the T-table or the
-//      bitsliced round function on the tile.  The LDS tables are filled once
-//      per workgroup; they do not depend on the key.
+//   2. persistent CTR kernel (a fixed grid of workgroups per CU): wave g of
+//      W takes tile g first, then claims tiles W + 16 k + p from one of 16
+//      counters p (its own, g mod 16, until that runs dry, then the next),
+//      finds the tile's segment with a 64-way ballot search over tile_start
+//      (three rounds for 10^4 segments), loads that segment's key schedule
+//      and nonce, and runs the T-table or the bitsliced round function on
+//      the tile.  The LDS tables are filled once per workgroup; they do not
+//      depend on the key.
 // Neither kernel uses a memset, so the pair can be captured in a HIP graph and
 // replayed after the segment table or the data have been rewritten in place.
 #include <hip/hip_runtime.h>
@@ -31,12 +33,22 @@ namespace {
 
 struct WsHeader {
     int32_t status;
-    uint32_t counter;
     uint32_t ntiles;
     uint32_t tile_blocks;
+    uint32_t unused;
 };
 
-constexpr size_t kWsHeader = 256;
+// Tile counters, each in a line of its own after the header line: atomic adds
+// on one address serialize (about 13 ns each, measured), adds on different
+// lines proceed side by side.
+constexpr uint32_t kClaimParts = 16;
+constexpr size_t kCounterStride = 256;
+constexpr size_t kWsHeader = kCounterStride * (kClaimParts + 1);
+
+__host__ __device__ __forceinline__ uint32_t *claim_counter(void *ws, uint32_t p)
+{
+    return reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + kCounterStride * (p + 1));
+}
 
 __device__ __forceinline__ uint32_t *tile_start_of(void *ws)
 {
@@ -122,10 +134,11 @@ __global__ __launch_bounds__(1024) void batched_prepare(const aes_segment_t *__r
         run += c;
     }
     __syncthreads();
+    if (tid < kClaimParts)
+        *claim_counter(ws, tid) = 0;
     if (tid == nt - 1) {
         start[nsegs] = part[nt - 1];
         h->ntiles = part[nt - 1];
-        h->counter = 0;
         h->tile_blocks = tile_blocks;
         h->status = bad_any ? (int32_t)AES_ERR_SEGMENT : (int32_t)AES_OK;
     }
@@ -153,18 +166,42 @@ __device__ __forceinline__ uint32_t find_segment(const uint32_t *__restrict__ st
     return lo;
 }
 
-// One tile per atomic add.  The single counter serializes the adds (about
-// 13 ns each, measured), which caps a launch near 75 M tiles/s: tiles of
-// 2048 blocks keep well below that.  Claiming chunks of consecutive tiles
-// per add lifted the cap but was slower at 2048-4096 blocks per tile (waves
-// then stream through separate regions instead of neighbouring tiles).
-__device__ __forceinline__ uint32_t claim_tile(WsHeader *h, uint32_t lane)
+// The next tile of a wave after its first (tile g of wave g), or ntiles when
+// none is left.  Counter p hands out tiles dyn0 + kClaimParts k + p, one per
+// atomic add; a wave starts at counter `part` and moves on to the next one
+// when it runs dry, so every tile is taken exactly once and waves that finish
+// early take work from the others.  Measured on the 10^4-message workload
+// (1,024-thread workgroups): one counter, 2,048-block tiles 0.480 ms and
+// 256-block tiles 2.20 ms (claim bound); static first tiles and 16 counters
+// 0.452 and 0.72 ms.  A plain load of the counter before each add (to skip
+// adds on counters already past the end) made every tile size slower, and
+// claiming chunks of consecutive tiles per add was slower at 2048-4096
+// blocks per tile (waves then stream through separate regions).
+__device__ __forceinline__ uint32_t claim_tile(void *ws, uint32_t &part, uint32_t dyn0,
+                                               uint32_t ntiles, uint32_t lane)
 {
-    uint32_t t = 0;
-    if (lane == 0)
-        t = atomicAdd(&h->counter, 1u);
-    return __builtin_amdgcn_readfirstlane(t);
+    for (uint32_t tried = 0; tried < kClaimParts; ++tried) {
+        uint32_t t = ntiles;
+        if (lane == 0 && (uint64_t)dyn0 + part < ntiles) {
+            const uint64_t t2 =
+                (uint64_t)dyn0 + (uint64_t)atomicAdd(claim_counter(ws, part), 1u) * kClaimParts + part;
+            if (t2 < ntiles)
+                t = (uint32_t)t2;
+        }
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t < ntiles)
+            return t;
+        part = part + 1 == kClaimParts ? 0u : part + 1;
+    }
+    return ntiles;
 }
+
+// Wave index in the grid and the number of waves.
+__device__ __forceinline__ uint32_t grid_wave()
+{
+    return blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+__device__ __forceinline__ uint32_t grid_waves() { return gridDim.x * (blockDim.x >> 6); }
 
 // A segment whose key schedule has no valid round count: its tiles are
 // skipped (the output stays untouched) and the status word says so.  Every
@@ -270,10 +307,9 @@ __global__ __launch_bounds__(1024) void batched_ttable_kernel(
     WsHeader *h = static_cast<WsHeader *>(ws);
     const uint32_t *start = tile_start_of(ws);
     const uint32_t ntiles = h->ntiles, tile_blocks = h->tile_blocks;
-    for (;;) {
-        const uint32_t t = claim_tile(h, lane);
-        if (t >= ntiles)
-            break;
+    const uint32_t nw = grid_waves();
+    uint32_t part = grid_wave() % kClaimParts;
+    for (uint32_t t = grid_wave(); t < ntiles; t = claim_tile(ws, part, nw, ntiles, lane)) {
         const uint32_t s = find_segment(start, nsegs, t, lane);
         const TileJob j = make_job(segs, start, s, t, tile_blocks, ks_table, in_base, out_base);
         switch (j.ks->nr) {
@@ -303,10 +339,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     WsHeader *h = static_cast<WsHeader *>(ws);
     const uint32_t *start = tile_start_of(ws);
     const uint32_t ntiles = h->ntiles, tile_blocks = h->tile_blocks;
-    for (;;) {
-        const uint32_t t = claim_tile(h, lane);
-        if (t >= ntiles)
-            break;
+    const uint32_t nw = grid_waves();
+    uint32_t part = grid_wave() % kClaimParts;
+    for (uint32_t t = grid_wave(); t < ntiles; t = claim_tile(ws, part, nw, ntiles, lane)) {
         const uint32_t s = find_segment(start, nsegs, t, lane);
         const TileJob j = make_job(segs, start, s, t, tile_blocks, ks_table, in_base, out_base);
         switch (j.ks->nr) {
@@ -326,6 +361,34 @@ size_t batched_workspace_bytes(uint32_t nsegs)
     return (bytes + 255u) & ~(size_t)255u;
 }
 
+void batched_prepare_host(const aes_segment_t *segs, uint32_t nsegs, uint32_t tile_blocks,
+                          void *ws_host)
+{
+    WsHeader *h = static_cast<WsHeader *>(ws_host);
+    uint32_t *start = reinterpret_cast<uint32_t *>(static_cast<char *>(ws_host) + kWsHeader);
+    uint32_t t = 0;
+    for (uint32_t s = 0; s < nsegs; ++s) {
+        start[s] = t;
+        t += (uint32_t)((((segs[s].nbytes + 15u) >> 4) + tile_blocks - 1) / tile_blocks);
+    }
+    start[nsegs] = t;
+    h->status = (int32_t)AES_OK;
+    h->ntiles = t;
+    h->tile_blocks = tile_blocks;
+    for (uint32_t p = 0; p < kClaimParts; ++p)
+        *claim_counter(ws_host, p) = 0;
+}
+
+hipError_t batched_ctr_prepared(const aes_segment_t *segs, uint32_t nsegs,
+                                const aes_key_schedule_t *ks_table, const uint8_t *in_base,
+                                uint8_t *out_base, void *ws, hipStream_t stream)
+{
+    const int cu = device_cu_count() > 0 ? device_cu_count() : 256;
+    hipLaunchKernelGGL(batched_ttable_kernel, dim3((uint32_t)cu), dim3(1024), 0, stream, segs,
+                       nsegs, ks_table, in_base, out_base, ws);
+    return hipGetLastError();
+}
+
 hipError_t batched_ctr(const aes_segment_t *segs, uint32_t nsegs,
                        const aes_key_schedule_t *ks_table, uint32_t nkeys,
                        const uint8_t *in_base, uint8_t *out_base,
@@ -337,7 +400,7 @@ hipError_t batched_ctr(const aes_segment_t *segs, uint32_t nsegs,
     const bool bs = layout == AES_LAYOUT_BITSLICE;
     uint32_t wg = tune && tune->wg_size ? tune->wg_size : (bs ? 256u : 1024u);
     uint32_t per_cu = tune && tune->grid_per_cu ? tune->grid_per_cu : (bs ? 2u : 1u);
-    uint32_t tile = tune && tune->tile_blocks ? tune->tile_blocks : 2048u;
+    uint32_t tile = tune && tune->tile_blocks ? tune->tile_blocks : kBatchedTileBlocks;
     if (wg < 64 || wg % 64 || wg > (bs ? 256u : 1024u))
         return hipErrorInvalidConfiguration;
     if (bs && tile % 2048u)

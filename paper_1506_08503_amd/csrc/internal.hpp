@@ -71,6 +71,19 @@ hipError_t batched_ctr(const aes_segment_t *segs, uint32_t nsegs,
                        const uint8_t *in_base, uint8_t *out_base,
                        const aes_batch_tune_t *tune, void *ws, hipStream_t stream);
 
+// The prepare kernel's work done on the host, for callers that already hold
+// the segment table in host memory and have checked it: writes the workspace
+// header and tile_start[0..nsegs] into ws_host (batched_workspace_bytes(nsegs)
+// bytes), to be copied to the device workspace before the launch.
+void batched_prepare_host(const aes_segment_t *segs, uint32_t nsegs, uint32_t tile_blocks,
+                          void *ws_host);
+// The T-table persistent kernel alone (1,024 threads, one workgroup per CU)
+// over a workspace that batched_prepare_host filled with the given tile size.
+hipError_t batched_ctr_prepared(const aes_segment_t *segs, uint32_t nsegs,
+                                const aes_key_schedule_t *ks_table, const uint8_t *in_base,
+                                uint8_t *out_base, void *ws, hipStream_t stream);
+constexpr uint32_t kBatchedTileBlocks = 2048;   // default tile of the T-table kernel
+
 // Host key expansion into the public struct (api.hip).
 aes_status_t expand_key_host(const uint8_t *key, size_t key_bytes, aes_key_schedule_t *ks);
 
