@@ -318,7 +318,8 @@ aes_status_t aes_batched_graph_destroy(aes_batched_graph_t *graph);
  *    than the whole budget is rejected;
  *  - key schedules live in a device cache of nslots rows (LRU among rows no
  *    in-flight batch uses); missing keys are expanded on the device into
- *    their rows on the batch's stream;
+ *    their rows on the batch's stream; one batch takes at most
+ *    nslots / nstreams of the free rows, so batches can overlap;
  *  - a batch closes when one of nstreams launch slots is free and nothing
  *    runs, or the queued bytes reach max_batch_bytes, or the oldest queued
  *    request has waited window_s, or the whole trace has arrived; it runs as

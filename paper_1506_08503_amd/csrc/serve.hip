@@ -46,11 +46,12 @@ struct KeyCache {
 
     // Largest k <= kmax such that the distinct keys of requests [0, k) fit:
     // every key that misses, and every key that hits an unpinned row, needs
-    // one of the unpinned rows.  Then pins (and fills) the rows of that
-    // prefix.  Returns k (0: not even the first request fits now); `keys`
-    // gets the prefix's distinct keys, `fills` the (row, key) pairs to expand.
-    uint32_t take(const uint32_t *key_id, uint32_t kmax, std::vector<uint32_t> &keys,
-                  std::vector<std::pair<uint32_t, uint32_t>> &fills)
+    // one of the unpinned rows, and at most row_cap of them are taken.  Then
+    // pins (and fills) the rows of that prefix.  Returns k (0: not even the
+    // first request fits now); `keys` gets the prefix's distinct keys,
+    // `fills` the (row, key) pairs to expand.
+    uint32_t take(const uint32_t *key_id, uint32_t kmax, uint32_t row_cap,
+                  std::vector<uint32_t> &keys, std::vector<std::pair<uint32_t, uint32_t>> &fills)
     {
         ++stamp;
         keys.clear();
@@ -62,7 +63,7 @@ struct KeyCache {
                 continue;
             const int64_t row = slot_of[key];
             const bool takes = row < 0 || pins[row] == 0;
-            if (takes && need + 1 > unpinned)
+            if (takes && (need + 1 > unpinned || need + 1 > row_cap))
                 break;
             seen[key] = stamp;
             need += takes;
@@ -190,6 +191,10 @@ aes_status_t serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8
     using clock = std::chrono::steady_clock;
     const uint32_t nstreams = pr.nstreams, maxb = pr.max_batch_reqs;
     const uint32_t nfill = std::min<uint32_t>(maxb, pr.nslots);
+    // Rows one batch may take from the unpinned ones: with the whole cache a
+    // batch of a small cache pins every row and the next batch cannot start
+    // until it ends; a share per stream lets batches overlap.
+    const uint32_t row_cap = std::max<uint32_t>(1, pr.nslots / nstreams);
     // footprint = input + 16-padded output; prefix sums of footprint and bytes
     std::vector<uint64_t> fp(nreq), cum_fp(nreq + 1, 0), cum_b(nreq + 1, 0);
     std::vector<uint32_t> key_id(nreq);
@@ -282,7 +287,7 @@ aes_status_t serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8
                               (cum_b.begin() + qh + 1);
                 k = std::min<uint64_t>({k, std::max<uint64_t>(kb, 1), maxb, arrived - qh});
                 if (k)
-                    k = kc.take(key_id.data() + qh, (uint32_t)k, keys, fills);
+                    k = kc.take(key_id.data() + qh, (uint32_t)k, row_cap, keys, fills);
                 if (k) {
                     uint32_t si = 0;
                     while (res.slots[si].busy)
