@@ -323,9 +323,10 @@ aes_status_t aes_batched_graph_destroy(aes_batched_graph_t *graph);
  *  - a batch closes when one of nstreams launch slots is free and nothing
  *    runs, or the queued bytes reach max_batch_bytes, or the oldest queued
  *    request has waited window_s, or the whole trace has arrived; it runs as
- *    aes_ctr_xcrypt_batched's T-table kernel (tiles of 1,024 blocks), with the
- *    tile table computed on the host and sent in the same copy as the
- *    segments and key fills, and batches on different streams overlap;
+ *    aes_ctr_xcrypt_batched's T-table kernel (tiles of 256 to 1,024 blocks
+ *    by batch size), with the tile table computed on the host and sent in
+ *    the same copy as the segments and key fills, and batches on different
+ *    streams overlap;
  *  - a request's result is the CTR encryption of its payload with its key,
  *    nonce and ctr0, exactly as aes_ctr_xcrypt would give it alone.
  */

@@ -168,12 +168,23 @@ struct Resources {
     }
 };
 
-// Tile of the batched kernel for serving batches.  Measured with 1,024 key
-// rows and the lognormal request mix (median 4 KiB): 1,024 blocks gave 25.6-
-// 25.9 M requests/s closed loop and p50/p99 latency 0.115/0.152 ms at 14 M
-// requests/s offered; 2,048 blocks 23.3-23.9 M/s and 0.19/0.26 ms; 512
-// blocks 20.1 M/s (more claims per batch).
-constexpr uint32_t kServeTileBlocks = 1024;
+// Tile of the batched kernel for a serving batch of `blocks` blocks.  A wave
+// works through a tile alone, so a batch with fewer tiles than the grid has
+// waves takes as long as one wave's tile: small batches get small tiles.
+// Large ones keep 1,024 blocks, where fewer tiles cost less per-tile set-up.
+// Measured (1,024 key rows, lognormal mix, median 4 KiB): 1,024-block tiles
+// 26.3-27.0 M requests/s closed loop and p50/p99 0.088/0.116 ms at 8 M
+// requests/s offered (batches of ~400, ~12 MB); 256-block tiles 22.4 M/s but
+// p50 0.065 ms at 8 M/s, and p99 0.22 ms at 14 M/s; 100 messages of 32 KiB
+// take 33.8 us with 1,024-block tiles and 20.1 us with 256.
+inline uint32_t serve_tile(uint64_t blocks, uint32_t waves)
+{
+    if (blocks <= 128ull * waves)
+        return 256;
+    if (blocks <= 256ull * waves)
+        return 512;
+    return 1024;
+}
 
 inline uint64_t pad16(uint64_t n) { return (n + 15u) & ~(uint64_t)15u; }
 inline size_t pad256(size_t n) { return (n + 255u) & ~(size_t)255u; }
@@ -195,6 +206,8 @@ aes_status_t serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8
     // batch of a small cache pins every row and the next batch cannot start
     // until it ends; a share per stream lets batches overlap.
     const uint32_t row_cap = std::max<uint32_t>(1, pr.nslots / nstreams);
+    // waves of the batched kernel's grid (one 1,024-thread workgroup per CU)
+    const uint32_t waves = 16u * (uint32_t)(device_cu_count() > 0 ? device_cu_count() : 256);
     // footprint = input + 16-padded output; prefix sums of footprint and bytes
     std::vector<uint64_t> fp(nreq), cum_fp(nreq + 1, 0), cum_b(nreq + 1, 0);
     std::vector<uint32_t> key_id(nreq);
@@ -324,7 +337,7 @@ aes_status_t serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8
                         out_off[qh + j] = arena + off;
                         off += pad16(r.nbytes);
                     }
-                    batched_prepare_host(sh, (uint32_t)k, kServeTileBlocks, s.stage_h);
+                    batched_prepare_host(sh, (uint32_t)k, serve_tile(off >> 4, waves), s.stage_h);
                     s.filled_rows.clear();
                     uint8_t *kh = s.stage_h + ws_b + seg_b, *lh = kh + (size_t)f * 32;
                     uint32_t *rh = reinterpret_cast<uint32_t *>(lh + ((f + 3u) & ~3u));
