@@ -56,6 +56,13 @@ hipError_t expand_keys_to_slots(const uint8_t *keys32, const uint8_t *lens,
                                 const uint32_t *slots, uint32_t n, aes_key_schedule_t *table,
                                 hipStream_t stream);
 
+// Copy `bytes` (a multiple of 16) from pinned host memory src_host to dst_dev
+// and expand nfill keys (keys32 / lens / slots in host memory, as for
+// expand_keys_to_slots) into table, in one launch on `stream`.
+hipError_t stage_and_expand(const void *src_host, void *dst_dev, size_t bytes,
+                            const uint8_t *keys32, const uint8_t *lens, const uint32_t *slots,
+                            uint32_t nfill, aes_key_schedule_t *table, hipStream_t stream);
+
 // --- serving loop (serve.hip); arguments checked by aes_serve_run ----------
 constexpr uint32_t kServeMaxStreams = 8;
 constexpr uint32_t kServeMaxBatch = 65536;

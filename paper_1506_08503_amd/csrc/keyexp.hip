@@ -5,6 +5,8 @@
 // data, instead of being expanded on the host and copied over.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "aes_tables.hpp"
 #include "internal.hpp"
 #include "keysched.hpp"
@@ -89,7 +91,56 @@ __global__ __launch_bounds__(256) void expand_keys_slots_kernel(
         expand_at<8>(key, out, sbox);
 }
 
+// The serving loop's staging step in one launch: copy n16 16-byte words from
+// pinned host memory to the device, and expand nfill keys (read from the same
+// host staging) into their rows, so that a batch needs no separate copy and
+// no second dependent launch before its CTR kernel.
+struct alignas(16) Word16 {
+    uint32_t w[4];
+};
+
+__global__ __launch_bounds__(256) void stage_expand_kernel(
+    const Word16 *__restrict__ src, Word16 *__restrict__ dst, uint32_t n16,
+    const uint8_t *__restrict__ keys32, const uint8_t *__restrict__ lens,
+    const uint32_t *__restrict__ slots, uint32_t nfill, aes_key_schedule_t *__restrict__ table)
+{
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+    for (uint32_t i = tid; i < n16; i += nt)
+        dst[i] = src[i];
+    if (nfill == 0)
+        return;
+    __shared__ uint8_t sbox[256];
+    for (uint32_t i = threadIdx.x; i < 256u; i += blockDim.x)
+        sbox[i] = g_sbox[i];
+    __syncthreads();
+    for (uint32_t k = tid; k < nfill; k += nt) {
+        const uint8_t *key = keys32 + 32u * k;
+        aes_key_schedule_t *out = table + slots[k];
+        if (lens[k] == 16)
+            expand_at<4>(key, out, sbox);
+        else if (lens[k] == 24)
+            expand_at<6>(key, out, sbox);
+        else
+            expand_at<8>(key, out, sbox);
+    }
+}
+
 }  // namespace
+
+hipError_t stage_and_expand(const void *src_host, void *dst_dev, size_t bytes,
+                            const uint8_t *keys32, const uint8_t *lens, const uint32_t *slots,
+                            uint32_t nfill, aes_key_schedule_t *table, hipStream_t stream)
+{
+    if (bytes % 16u || bytes / 16u > 0xffffffffull)
+        return hipErrorInvalidValue;
+    const uint32_t n16 = (uint32_t)(bytes / 16u);
+    const uint32_t need = std::max<uint32_t>((n16 + 255u) / 256u, (nfill + 255u) / 256u);
+    const uint32_t grid = std::min<uint32_t>(std::max<uint32_t>(need, 1u), 1024u);
+    hipLaunchKernelGGL(stage_expand_kernel, dim3(grid), dim3(256), 0, stream,
+                       static_cast<const Word16 *>(src_host), static_cast<Word16 *>(dst_dev), n16,
+                       keys32, lens, slots, nfill, table);
+    return hipGetLastError();
+}
 
 hipError_t expand_keys_to_slots(const uint8_t *keys32, const uint8_t *lens,
                                 const uint32_t *slots, uint32_t n, aes_key_schedule_t *table,

@@ -129,15 +129,17 @@ struct KeyCache {
     }
 };
 
-// Per-stream launch slot: staging for one batch at a time.  A batch of k
-// requests with f key fills goes over in one copy, laid out the same way in
-// pinned host memory and on the device:
+// Per-stream launch slot: staging for one batch at a time, k requests with f
+// key fills, in pinned host memory:
 //   [workspace: header + tile_start[0..k]] [k segments] [f keys32 | f lens | f rows]
 // the workspace written on the host (the prepare kernel is not launched).
+// One kernel copies the workspace and the segments to the same offsets of
+// the device staging and expands the fills straight from host memory.
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr, filled = nullptr;
-    uint8_t *stage_h = nullptr;   // pinned
+    uint8_t *stage_h = nullptr;   // pinned, mapped
+    uint8_t *stage_hd = nullptr;  // the same memory as the device addresses it
     uint8_t *stage_d = nullptr;
     bool busy = false;
     // the batch in flight
@@ -231,7 +233,8 @@ aes_status_t serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8
         if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&s.filled, hipEventDisableTiming) != hipSuccess ||
-            hipHostMalloc((void **)&s.stage_h, stage_max, 0) != hipSuccess ||
+            hipHostMalloc((void **)&s.stage_h, stage_max, hipHostMallocMapped) != hipSuccess ||
+            hipHostGetDevicePointer((void **)&s.stage_hd, s.stage_h, 0) != hipSuccess ||
             hipMalloc((void **)&s.stage_d, stage_max) != hipSuccess)
             return AES_ERR_HIP;
         s.rows.reserve(pr.nslots);
@@ -348,18 +351,15 @@ aes_status_t serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8
                         filled_by[fills[j].first] = (int32_t)si;
                         s.filled_rows.push_back(fills[j].first);
                     }
-                    const size_t total = ws_b + seg_b + (f ? fill_bytes(f) : 0);
-                    if (hipMemcpyAsync(s.stage_d, s.stage_h, total, hipMemcpyHostToDevice,
-                                       s.stream) != hipSuccess)
+                    // workspace and segments to the device, key fills read
+                    // from the pinned staging: one launch
+                    const size_t fo = ws_b + seg_b;   // fills' offset in the staging
+                    const uint8_t *kd = s.stage_hd + fo, *ld = kd + (size_t)f * 32;
+                    const uint32_t *rd = reinterpret_cast<const uint32_t *>(ld + ((f + 3u) & ~3u));
+                    if (stage_and_expand(s.stage_hd, s.stage_d, fo, kd, ld, rd, f, res.table,
+                                         s.stream) != hipSuccess ||
+                        (f && hipEventRecord(s.filled, s.stream) != hipSuccess))
                         return AES_ERR_HIP;
-                    if (f) {
-                        const uint8_t *kd = s.stage_d + ws_b + seg_b, *ld = kd + (size_t)f * 32;
-                        const uint32_t *rd =
-                            reinterpret_cast<const uint32_t *>(ld + ((f + 3u) & ~3u));
-                        if (expand_keys_to_slots(kd, ld, rd, f, res.table, s.stream) != hipSuccess ||
-                            hipEventRecord(s.filled, s.stream) != hipSuccess)
-                            return AES_ERR_HIP;
-                    }
                     if (batched_ctr_prepared(reinterpret_cast<const aes_segment_t *>(s.stage_d + ws_b),
                                              (uint32_t)k, res.table, pool, out, s.stage_d,
                                              s.stream) != hipSuccess ||
