@@ -51,14 +51,10 @@ hipError_t ghash(const uint32_t h_words[4], const void *x, uint64_t nblocks, voi
 // --- device key expansion (keyexp.hip) -------------------------------------
 hipError_t expand_keys_device(const uint8_t *keys, uint32_t key_bytes, uint64_t nkeys,
                               aes_key_schedule_t *ks, hipStream_t stream);
-// Key i: the first lens[i] bytes of keys32 + 32 i; its schedule -> table[slots[i]].
-hipError_t expand_keys_to_slots(const uint8_t *keys32, const uint8_t *lens,
-                                const uint32_t *slots, uint32_t n, aes_key_schedule_t *table,
-                                hipStream_t stream);
-
 // Copy `bytes` (a multiple of 16) from pinned host memory src_host to dst_dev
-// and expand nfill keys (keys32 / lens / slots in host memory, as for
-// expand_keys_to_slots) into table, in one launch on `stream`.
+// and expand nfill keys into table, in one launch on `stream`: key i is the
+// first lens[i] bytes (16, 24 or 32) of keys32 + 32 i and goes to row
+// slots[i] (keys32, lens and slots in mapped host memory).
 hipError_t stage_and_expand(const void *src_host, void *dst_dev, size_t bytes,
                             const uint8_t *keys32, const uint8_t *lens, const uint32_t *slots,
                             uint32_t nfill, aes_key_schedule_t *table, hipStream_t stream);

@@ -55,9 +55,7 @@ __global__ __launch_bounds__(256) void expand_keys_kernel(const uint8_t *__restr
         expand_one<8>(keys, k, out, sbox);
 }
 
-// Keys of mixed lengths into chosen rows of a schedule table: key i is the
-// first lens[i] bytes (16, 24 or 32) of keys32[32 i .. 32 i + 31] and its
-// schedule goes to table[slots[i]] (the serving loop's key cache fills).
+// One key of 4 NK bytes at `key` into the schedule record `out`.
 template <uint32_t NK>
 __device__ __forceinline__ void expand_at(const uint8_t *__restrict__ key,
                                           aes_key_schedule_t *__restrict__ out,
@@ -68,27 +66,6 @@ __device__ __forceinline__ void expand_at(const uint8_t *__restrict__ key,
     for (uint32_t i = 0; i < 4 * NK; ++i)
         k[i] = key[i];
     expand_schedule_nk<NK>(k, out, sbox);
-}
-
-__global__ __launch_bounds__(256) void expand_keys_slots_kernel(
-    const uint8_t *__restrict__ keys32, const uint8_t *__restrict__ lens,
-    const uint32_t *__restrict__ slots, uint32_t n, aes_key_schedule_t *__restrict__ table)
-{
-    __shared__ uint8_t sbox[256];
-    for (uint32_t i = threadIdx.x; i < 256u; i += blockDim.x)
-        sbox[i] = g_sbox[i];
-    __syncthreads();
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n)
-        return;
-    const uint8_t *key = keys32 + 32u * k;
-    aes_key_schedule_t *out = table + slots[k];
-    if (lens[k] == 16)
-        expand_at<4>(key, out, sbox);
-    else if (lens[k] == 24)
-        expand_at<6>(key, out, sbox);
-    else
-        expand_at<8>(key, out, sbox);
 }
 
 // The serving loop's staging step in one launch: copy n16 16-byte words from
@@ -139,17 +116,6 @@ hipError_t stage_and_expand(const void *src_host, void *dst_dev, size_t bytes,
     hipLaunchKernelGGL(stage_expand_kernel, dim3(grid), dim3(256), 0, stream,
                        static_cast<const Word16 *>(src_host), static_cast<Word16 *>(dst_dev), n16,
                        keys32, lens, slots, nfill, table);
-    return hipGetLastError();
-}
-
-hipError_t expand_keys_to_slots(const uint8_t *keys32, const uint8_t *lens,
-                                const uint32_t *slots, uint32_t n, aes_key_schedule_t *table,
-                                hipStream_t stream)
-{
-    if (n == 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(expand_keys_slots_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
-                       keys32, lens, slots, n, table);
     return hipGetLastError();
 }
 
