@@ -54,7 +54,8 @@ hipError_t expand_keys_device(const uint8_t *keys, uint32_t key_bytes, uint64_t 
 // Copy `bytes` (a multiple of 16) from pinned host memory src_host to dst_dev
 // and expand nfill keys into table, in one launch on `stream`: key i is the
 // first lens[i] bytes (16, 24 or 32) of keys32 + 32 i and goes to row
-// slots[i] (keys32, lens and slots in mapped host memory).
+// slots[i] (keys32, lens and slots in mapped host memory); rows get nr,
+// key_bytes and rk_enc, not rk_dec.
 hipError_t stage_and_expand(const void *src_host, void *dst_dev, size_t bytes,
                             const uint8_t *keys32, const uint8_t *lens, const uint32_t *slots,
                             uint32_t nfill, aes_key_schedule_t *table, hipStream_t stream);

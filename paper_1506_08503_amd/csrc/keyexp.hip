@@ -55,22 +55,24 @@ __global__ __launch_bounds__(256) void expand_keys_kernel(const uint8_t *__restr
         expand_one<8>(keys, k, out, sbox);
 }
 
-// One key of 4 NK bytes at `key` into the schedule record `out`.
+// One key of 4 NK bytes at `key` into the schedule record `out`: round count,
+// key size and encryption round keys (the serving table is read by the CTR
+// kernel only, so the decryption keys are not computed).
 template <uint32_t NK>
-__device__ __forceinline__ void expand_at(const uint8_t *__restrict__ key,
-                                          aes_key_schedule_t *__restrict__ out,
-                                          const uint8_t *sbox)
+__device__ __forceinline__ void expand_enc_at(const uint8_t *__restrict__ key,
+                                              aes_key_schedule_t *__restrict__ out,
+                                              const uint8_t *sbox)
 {
     uint8_t k[4 * NK];
 #pragma unroll
     for (uint32_t i = 0; i < 4 * NK; ++i)
         k[i] = key[i];
-    expand_schedule_nk<NK>(k, out, sbox);
+    expand_schedule_nk<NK, false>(k, out, sbox);
 }
 
 // The serving loop's staging step in one launch: copy n16 16-byte words from
 // pinned host memory to the device, and expand nfill keys (read from the same
-// host staging) into their rows, so that a batch needs no separate copy and
+// host staging) into their rows (encryption keys only), so that a batch needs no separate copy and
 // no second dependent launch before its CTR kernel.
 struct alignas(16) Word16 {
     uint32_t w[4];
@@ -94,11 +96,11 @@ __global__ __launch_bounds__(256) void stage_expand_kernel(
         const uint8_t *key = keys32 + 32u * k;
         aes_key_schedule_t *out = table + slots[k];
         if (lens[k] == 16)
-            expand_at<4>(key, out, sbox);
+            expand_enc_at<4>(key, out, sbox);
         else if (lens[k] == 24)
-            expand_at<6>(key, out, sbox);
+            expand_enc_at<6>(key, out, sbox);
         else
-            expand_at<8>(key, out, sbox);
+            expand_enc_at<8>(key, out, sbox);
     }
 }
 

@@ -49,8 +49,9 @@ __host__ __device__ inline uint32_t ks_inv_mix(uint32_t w)
 }
 
 // The schedule for Nk = NK key words; every index is a compile-time constant
-// so the words stay in registers on the device.
-template <uint32_t NK>
+// so the words stay in registers on the device.  DEC = false leaves rk_dec
+// unwritten (for tables that only counter mode reads).
+template <uint32_t NK, bool DEC = true>
 __host__ __device__ inline void expand_schedule_nk(const uint8_t *key, aes_key_schedule_t *ks,
                                                    const uint8_t *sbox)
 {
@@ -79,6 +80,8 @@ __host__ __device__ inline void expand_schedule_nk(const uint8_t *key, aes_key_s
 #pragma unroll
     for (uint32_t i = 0; i < 60; ++i)
         ks->rk_enc[i] = i < nw ? w[i] : 0u;
+    if (!DEC)
+        return;
 #pragma unroll
     for (uint32_t c = 0; c < 4; ++c) {
         ks->rk_dec[c] = w[4 * nr + c];

@@ -224,6 +224,8 @@ aes_status_t serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8
 
     Resources res;
     KeyCache kc(nkeys, pr.nslots);
+    // the key cache's rows: nr, key_bytes and rk_enc are written on a fill
+    // (counter mode reads nothing else)
     if (hipMalloc(&res.table, sizeof(aes_key_schedule_t) * pr.nslots) != hipSuccess)
         return AES_ERR_HIP;
     const size_t stage_max = batched_workspace_bytes(maxb) +
