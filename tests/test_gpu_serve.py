@@ -108,3 +108,33 @@ def test_native_rejects_oversize():
     assert st.rejected == 1 and st.completed == 199
     assert res[7] is None and np.isinf(st.latency_s[7])
     assert res[8] is not None and res[8].numel() == int(reqs.size[8])
+
+
+@pytest.mark.parametrize("max_batch_mib", [4, 12, 48])
+def test_native_batch_sizes_cover_every_tile(oracle, max_batch_mib):
+    """Backlogged requests of up to 2 MiB cut into batches of about
+    max_batch_mib MiB: the loop runs them with 256-, 512- and 1,024-block
+    tiles respectively; every output equals the request run alone, and a
+    sample equals the oracle."""
+    nreq, pool_bytes = 400, 64 << 20
+    rs = wl.serving_inputs(nreq, 1e5, nkeys=24, median=128 << 10, sigma=1.0,
+                           max_size=2 << 20, seed=40 + max_batch_mib)
+    reqs = serve.requests_from_stream(rs, pool_bytes, seed=41)
+    g = np.random.Generator(np.random.PCG64(42))
+    pool_h = np.frombuffer(g.bytes(pool_bytes), np.uint8).copy()
+    pool = torch.from_numpy(pool_h).to(DEV)
+    st, res = serve.run_native(pool, rs.keys, reqs, nslots=8, nstreams=2, hbm_budget=1 << 30,
+                               max_batch_bytes=max_batch_mib << 20, realtime=False)
+    torch.cuda.synchronize()
+    assert st.completed == nreq and st.rejected == 0
+    assert st.batches >= int(reqs.size.sum()) // ((max_batch_mib + 2) << 20)
+    for i in range(nreq):
+        a, n = int(reqs.in_off[i]), int(reqs.size[i])
+        ks = am.key_schedule(rs.keys[reqs.key_id[i]], DEV)
+        alone = am.ctr_xcrypt(ks, reqs.nonce[i].tobytes(), int(reqs.ctr0[i]), pool[a:a + n])
+        assert torch.equal(res[i], alone), i
+    for i in range(0, nreq, 40):
+        a, n = int(reqs.in_off[i]), int(reqs.size[i])
+        exp = oracle.ctr_xcrypt(rs.keys[reqs.key_id[i]], reqs.nonce[i].tobytes(),
+                                int(reqs.ctr0[i]), pool_h[a:a + n])
+        assert np.array_equal(res[i].cpu().numpy(), exp), i
