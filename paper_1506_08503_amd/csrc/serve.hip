@@ -260,7 +260,6 @@ aes_status_t serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8
         // requests are sorted by arrival time
         while (arrived < nreq && reqs[arrived].arrival_s <= now)
             ++arrived;
-        bool progressed = false;
         // retire finished batches
         for (uint32_t si = 0; si < nstreams; ++si) {
             Slot &s = res.slots[si];
@@ -283,13 +282,11 @@ aes_status_t serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8
             st.bytes += s.bytes;
             s.busy = false;
             --inflight;
-            progressed = true;
         }
         // reject what can never fit
         while (qh < arrived && fp[qh] > pr.hbm_budget) {
             ++st.rejected;
             ++qh;
-            progressed = true;
         }
         if (qh < arrived && inflight < nstreams) {
             const uint64_t queued = cum_b[arrived] - cum_b[qh];
@@ -382,11 +379,9 @@ aes_status_t serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8
                     st.max_inflight = std::max(st.max_inflight, inflight);
                     st.max_held = std::max(st.max_held, held);
                     qh += k;
-                    progressed = true;
                 }
             }
         }
-        (void)progressed;
     }
     st.elapsed_s = now_s();
     for (size_t i = 0; i < nreq; ++i)
