@@ -179,12 +179,12 @@ def serving_leg(nreq):
             ex = serve.GpuExecutor(pool, rs.keys, nslots, nstreams=2, max_segs=8192,
                                    out_arena_bytes=4 << 30)
             srv = serve.Server(ex, serve.KeyCache(nslots, len(rs.keys)), hbm_budget=4 << 30,
-                               max_batch_reqs=8192, window_s=50e-6)
+                               max_batch_reqs=8192, window_s=25e-6)
             st, _ = srv.run(reqs)
         else:
             st, _ = serve.run_native(pool, rs.keys, reqs, nslots, nstreams=2,
                                      hbm_budget=4 << 30, max_batch_reqs=8192,
-                                     window_s=50e-6, out=out_for(reqs))
+                                     window_s=25e-6, out=out_for(reqs))
         torch.cuda.synchronize()
         s = st.summary(skip=warm)
         if warm:

@@ -238,7 +238,7 @@ class Server:
 
     def __init__(self, executor, key_cache: KeyCache, hbm_budget: int,
                  max_batch_bytes: int = 64 << 20, max_batch_reqs: int = 8192,
-                 window_s: float = 50e-6, clock=time.perf_counter):
+                 window_s: float = 25e-6, clock=time.perf_counter):
         self.ex = executor
         self.kc = key_cache
         self.budget = hbm_budget
@@ -531,7 +531,7 @@ class NativeResults:
 
 def run_native(pool, keys: list, reqs: Requests, nslots: int, nstreams: int = 2,
                hbm_budget: int = 4 << 30, max_batch_reqs: int = 8192,
-               max_batch_bytes: int = 64 << 20, window_s: float = 50e-6,
+               max_batch_bytes: int = 64 << 20, window_s: float = 25e-6,
                realtime: bool = True, out=None):
     """The same request loop as Server with GpuExecutor, run in the library
     (aes_serve_run): admission, the key-schedule cache, batch formation and
