@@ -317,16 +317,16 @@ aes_status_t aes_batched_graph_destroy(aes_batched_graph_t *graph);
  *    bytes of admitted, unfinished requests fit hbm_budget; a request larger
  *    than the whole budget is rejected;
  *  - key schedules live in a device cache of nslots rows (LRU among rows no
- *    in-flight batch uses); missing keys are expanded on the device into
- *    their rows on the batch's stream; one batch takes at most
+ *    in-flight batch uses, empty rows first); one batch takes at most
  *    nslots / nstreams of the free rows, so batches can overlap;
  *  - a batch closes when one of nstreams launch slots is free and nothing
  *    runs, or the queued bytes reach max_batch_bytes, or the oldest queued
- *    request has waited window_s, or the whole trace has arrived; it runs as
- *    aes_ctr_xcrypt_batched's T-table kernel (tiles of 256 to 1,024 blocks
- *    by batch size), with the tile table computed on the host and sent in
- *    the same copy as the segments and key fills, and batches on different
- *    streams overlap;
+ *    request has waited window_s, or the whole trace has arrived.  On the
+ *    batch's stream one staging kernel copies its segment and tile tables
+ *    (written on the host into mapped pinned memory) to the device and
+ *    expands its missed keys into their rows, then aes_ctr_xcrypt_batched's
+ *    T-table kernel runs it (tiles of 256 to 1,024 blocks by batch size);
+ *    batches on different streams overlap;
  *  - a request's result is the CTR encryption of its payload with its key,
  *    nonce and ctr0, exactly as aes_ctr_xcrypt would give it alone.
  */
@@ -378,10 +378,13 @@ typedef struct aes_serve_stats {
  * in_off not 16-aligned), AES_ERR_SEGMENT (a payload outside the pool, a
  * key_id >= nkeys, nbytes == 0, reserved != 0, ctr0 + blocks > 2^32, or
  * arrivals out of order), AES_ERR_CONFIG (parameters out of range, or out_bytes
- * smaller than the sum of the padded payloads).  Unlike the other entry
- * points this one allocates: the device key table and per-stream staging,
- * streams and events (set up before the clock starts, freed at the end).
- * Blocks the calling thread for the whole run; uses the current device.
+ * smaller than the sum of the padded payloads); AES_ERR_HIP if a HIP call
+ * fails during the run (outputs and latencies are then incomplete).  Unlike
+ * the other entry points this one allocates: the device key table, per-stream
+ * pinned and device staging, streams and events (set up before the clock
+ * starts, freed before it returns).  Blocks the calling thread for the whole
+ * run, polling the device; uses the current device.  The pool must not be
+ * written while the call runs.
  */
 aes_status_t aes_serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8_t *keys32,
                            const uint8_t *key_len, size_t nkeys, const void *pool_dev,
