@@ -138,3 +138,30 @@ def test_native_batch_sizes_cover_every_tile(oracle, max_batch_mib):
         exp = oracle.ctr_xcrypt(rs.keys[reqs.key_id[i]], reqs.nonce[i].tobytes(),
                                 int(reqs.ctr0[i]), pool_h[a:a + n])
         assert np.array_equal(res[i].cpu().numpy(), exp), i
+
+
+def test_native_all_key_sizes(oracle):
+    """Keys of 16, 24 and 32 bytes in one trace (the staging kernel expands
+    each size into the cache); 8 rows for 30 keys so rows are refilled with
+    keys of other sizes."""
+    nreq, pool_bytes = 1500, 16 << 20
+    rs = wl.serving_inputs(nreq, 2e5, nkeys=30, median=2048, sigma=1.5, max_size=256 << 10,
+                           seed=51)
+    g = np.random.Generator(np.random.PCG64(52))
+    rs.keys = [g.bytes((16, 24, 32)[i % 3]) for i in range(30)]
+    reqs = serve.requests_from_stream(rs, pool_bytes, seed=53)
+    pool_h = np.frombuffer(g.bytes(pool_bytes), np.uint8).copy()
+    pool = torch.from_numpy(pool_h).to(DEV)
+    st, res = serve.run_native(pool, rs.keys, reqs, nslots=8, nstreams=2)
+    torch.cuda.synchronize()
+    assert st.completed == nreq and st.key_misses > 30
+    for i in range(nreq):
+        a, n = int(reqs.in_off[i]), int(reqs.size[i])
+        ks = am.key_schedule(rs.keys[reqs.key_id[i]], DEV)
+        alone = am.ctr_xcrypt(ks, reqs.nonce[i].tobytes(), int(reqs.ctr0[i]), pool[a:a + n])
+        assert torch.equal(res[i], alone), i
+    for i in range(0, nreq, 50):
+        a, n = int(reqs.in_off[i]), int(reqs.size[i])
+        exp = oracle.ctr_xcrypt(rs.keys[reqs.key_id[i]], reqs.nonce[i].tobytes(),
+                                int(reqs.ctr0[i]), pool_h[a:a + n])
+        assert np.array_equal(res[i].cpu().numpy(), exp), i
