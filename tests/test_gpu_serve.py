@@ -143,13 +143,17 @@ def test_native_batch_sizes_cover_every_tile(oracle, max_batch_mib):
 def test_native_all_key_sizes(oracle):
     """Keys of 16, 24 and 32 bytes in one trace (the staging kernel expands
     each size into the cache); 8 rows for 30 keys so rows are refilled with
-    keys of other sizes."""
+    keys of other sizes; every other request starts at a random counter."""
     nreq, pool_bytes = 1500, 16 << 20
     rs = wl.serving_inputs(nreq, 2e5, nkeys=30, median=2048, sigma=1.5, max_size=256 << 10,
                            seed=51)
     g = np.random.Generator(np.random.PCG64(52))
     rs.keys = [g.bytes((16, 24, 32)[i % 3]) for i in range(30)]
     reqs = serve.requests_from_stream(rs, pool_bytes, seed=53)
+    # half the requests start at a random counter (not group aligned), up to
+    # the last one that still fits the request
+    r = g.integers(0, (1 << 32) - (reqs.size + 15) // 16, dtype=np.int64)
+    reqs.ctr0 = np.where(np.arange(nreq) % 2 == 1, r, 0).astype(np.uint32)
     pool_h = np.frombuffer(g.bytes(pool_bytes), np.uint8).copy()
     pool = torch.from_numpy(pool_h).to(DEV)
     st, res = serve.run_native(pool, rs.keys, reqs, nslots=8, nstreams=2)
