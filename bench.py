@@ -177,8 +177,8 @@ def serving_leg(nreq):
         return out[0]
 
     def run(rate, n, nslots, closed=False, python_loop=False):
-        warm = 0 if closed else SERVING_WARMUP
-        rs = wl.serving_inputs(n + warm, rate, nkeys=1024)
+        nwarm = 0 if closed else SERVING_WARMUP
+        rs = wl.serving_inputs(n + nwarm, rate, nkeys=1024)
         reqs = serve.requests_from_stream(rs, pool_bytes)
         if closed:
             reqs.arrival[:] = 0.0
@@ -195,9 +195,9 @@ def serving_leg(nreq):
                                      hbm_budget=4 << 30, max_batch_reqs=8192,
                                      window_s=25e-6, out=ob)
         torch.cuda.synchronize()
-        s = st.summary(skip=warm)
-        if warm:
-            s["warmup_requests"] = warm
+        s = st.summary(skip=nwarm)
+        if nwarm:
+            s["warmup_requests"] = nwarm
             s["p99_ms_all"] = st.summary()["p99_ms"]
         return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
 
