@@ -57,7 +57,8 @@ def test_served_equals_alone(oracle):
     assert s["p99_ms"] >= s["p50_ms"] > 0
 
 
-@pytest.mark.parametrize("nstreams,realtime", [(2, True), (4, False), (1, True)])
+@pytest.mark.parametrize("nstreams,realtime", [(2, True), (4, False), (1, True), (3, True),
+                                               (8, False)])
 def test_native_served_equals_alone(oracle, nstreams, realtime):
     """The request loop run inside the library (aes_serve_run): every request
     equals the same request run alone and the oracle's CTR; a 16-row key
