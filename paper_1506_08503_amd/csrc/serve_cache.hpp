@@ -28,6 +28,8 @@ struct ServeKeyCache {
     std::vector<uint64_t> hit_row;   // per row: stamp when a key of that batch hit it
     uint64_t tick = 0, stamp = 0, hits = 0, misses = 0;
     uint32_t unpinned = 0;
+    std::vector<uint64_t> cand;      // scratch of take(): victim candidates
+    std::vector<uint32_t> missing;   // scratch of take(): keys to fill
 
     ServeKeyCache(size_t nkeys, uint32_t nslots)
         : slot_of(nkeys, -1), key_of(nslots, -1), last_use(nslots, 0), pins(nslots, 0),
@@ -71,30 +73,24 @@ struct ServeKeyCache {
                 ++nmiss;
         }
         if (nmiss) {
-            std::vector<uint32_t> cand;
+            // victims: empty rows first, then the least recently used, ties
+            // by row.  A row is empty exactly while its last_use is 0 (rows
+            // are refilled, never emptied, and ticks start at 1), so that
+            // order is the order of last_use << 32 | row.
+            cand.clear();
             for (uint32_t r = 0; r < key_of.size(); ++r)
                 if (pins[r] == 0 && hit_row[r] != stamp)
-                    cand.push_back(r);
-            // victims: empty rows first, then the least recently used, ties
-            // by row; the missing keys take them in ascending key order
-            std::partial_sort(cand.begin(), cand.begin() + nmiss, cand.end(),
-                              [&](uint32_t a, uint32_t b) {
-                                  const bool fa = key_of[a] >= 0, fb = key_of[b] >= 0;
-                                  if (fa != fb)
-                                      return !fa;
-                                  if (last_use[a] != last_use[b])
-                                      return last_use[a] < last_use[b];
-                                  return a < b;
-                              });
-            std::vector<uint32_t> missing;
-            missing.reserve(nmiss);
+                    cand.push_back(last_use[r] << 32 | r);
+            std::partial_sort(cand.begin(), cand.begin() + nmiss, cand.end());
+            // the missing keys take them in ascending key order
+            missing.clear();
             for (uint32_t key : keys)
                 if (slot_of[key] < 0)
                     missing.push_back(key);
             std::sort(missing.begin(), missing.end());
             uint32_t v = 0;
             for (uint32_t key : missing) {
-                const uint32_t row = cand[v++];
+                const uint32_t row = (uint32_t)cand[v++];
                 if (key_of[row] >= 0)
                     slot_of[key_of[row]] = -1;
                 key_of[row] = key;
