@@ -205,6 +205,27 @@ def test_bench_refuses_more_than_one_gpu():
     assert "one GPU" in r.stderr
 
 
+def test_bench_locals_do_not_shadow_its_functions():
+    """bench.py's GPU legs cannot run here; at least no function (or a
+    function nested in it) assigns a name that shadows a module-level function
+    it also calls, the mistake that would only surface on the GPU."""
+    import ast
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    tree = ast.parse(open(os.path.join(root, "bench.py")).read())
+    module_funcs = {n.name for n in tree.body if isinstance(n, ast.FunctionDef)}
+    bad = []
+    for fn in ast.walk(tree):
+        if not isinstance(fn, ast.FunctionDef):
+            continue
+        stored = {n.id for n in ast.walk(fn) if isinstance(n, ast.Name)
+                  and isinstance(n.ctx, ast.Store)}
+        stored |= {a.arg for a in fn.args.args}
+        called = {n.func.id for n in ast.walk(fn) if isinstance(n, ast.Call)
+                  and isinstance(n.func, ast.Name)}
+        bad += [(fn.name, x) for x in stored & called & module_funcs]
+    assert not bad, bad
+
+
 def test_serve_run_validation():
     """aes_serve_run checks every request and parameter before it sets
     anything up (no GPU is touched for these cases)."""
