@@ -171,8 +171,11 @@ def pin_mix_columns(o):
 
 # ------------------------------------------------------------ full cipher
 def pin_standard_vectors(o):
-    """FIPS-197 App. A/B/C and SP 800-38A F.5.1/F.5.5 known answers."""
+    """FIPS-197 App. A/B/C and SP 800-38A F.5.1/F.5.5 known answers; each ECB
+    and CTR line is also run through the system OpenSSL tool when it exists
+    (the key-schedule lines have no OpenSSL counterpart)."""
     kinds = set()
+    checked = 0
     for f in _lines("standard_vectors.txt"):
         kinds.add(f[0])
         if f[0] == "ecb":
@@ -180,6 +183,10 @@ def pin_standard_vectors(o):
             assert o.encrypt_block(key, pt).tobytes() == ct
             assert o.decrypt_block(key, ct).tobytes() == pt
             assert o.ecb_encrypt(key, np.frombuffer(pt, np.uint8)).tobytes() == ct
+            if openssl_cli.available():
+                assert openssl_cli.ecb_encrypt(key, pt).tobytes() == ct
+                assert openssl_cli.ecb_decrypt(key, ct).tobytes() == pt
+                checked += 1
         elif f[0] == "lastkey":
             nr, rk = o.expand_key(bytes.fromhex(f[1]))
             assert rk[:16].tobytes() == bytes.fromhex(f[1])[:16]
@@ -189,7 +196,11 @@ def pin_standard_vectors(o):
             ctr0 = int(f[3], 16)
             pt = np.frombuffer(bytes.fromhex(f[4]), np.uint8)
             assert o.ctr_xcrypt(key, nonce, ctr0, pt).tobytes() == bytes.fromhex(f[5])
+            if openssl_cli.available():
+                assert openssl_cli.ctr_xcrypt(key, nonce, ctr0, pt).tobytes() == bytes.fromhex(f[5])
+                checked += 1
     assert kinds == {"ecb", "lastkey", "ctr"}
+    assert checked == 0 or checked >= 6
 
 
 def pin_paper_vectorized(o):

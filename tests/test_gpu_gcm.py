@@ -192,9 +192,6 @@ def test_gcm_4gib_linearity_and_samples(oracle):
 
 
 @pytest.mark.slow
-@pytest.mark.skipif(os.environ.get("AESMI_FULL_COMPARE") != "1",
-                    reason="the oracle's 4 GiB keystream takes about a minute of host CPU; "
-                           "run with AESMI_FULL_COMPARE=1")
 def test_gcm_4gib_exact_tag(oracle):
     """4 GiB AES-128-GCM with the plaintext set to the oracle's own keystream
     (counters 2, 3, ...): every ciphertext byte must be 0, and the tag is then

@@ -321,9 +321,6 @@ def test_stream_sharded_equals_whole():
 
 
 @pytest.mark.slow
-@pytest.mark.skipif(os.environ.get("AESMI_FULL_COMPARE") != "1",
-                    reason="every byte of 4 GiB against the threaded oracle takes minutes of "
-                           "host CPU; run with AESMI_FULL_COMPARE=1")
 def test_stream_4gib_full_oracle(oracle):
     """Every byte of the 4 GiB AES-128 CTR output against the oracle, which
     recomputes the stream in 64 MiB pieces on all host threads."""
