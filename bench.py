@@ -65,6 +65,21 @@ def parse():
     p.add_argument("--sweep", action="store_true",
                    help="instead of the benchmark: the paper's Fig. 3 workloads (rate vs "
                         "number of 16-byte messages; rate vs length for 128 messages)")
+    p.add_argument("--no-sweep", action="store_true",
+                   help="leave the Fig. 3 workloads out of the benchmark line")
+    p.add_argument("--plaintext", choices=["random", "zero"], default="random",
+                   help="stream leg input: uniform random bytes (the workload) or all zero "
+                        "(for data-dependence checks of the counters)")
+    p.add_argument("--key-seed", type=int, default=None,
+                   help="draw the stream leg's key and nonce from this seed instead of the "
+                        "workload's (for key-dependence checks of the counters)")
+    p.add_argument("--no-tune", action="store_true",
+                   help="time the library's default launch shape instead of the autotuned one")
+    p.add_argument("--no-probes", action="store_true",
+                   help="leave out the on-chip ceiling microbenchmarks (LDS, rounds, VALU)")
+    p.add_argument("--roctx-timed", action="store_true",
+                   help="pause the profiler (roctx) except around the timed steps: with "
+                        "rocprofv3 --selected-regions only those steps are traced")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     return p.parse_args()
 
@@ -259,6 +274,87 @@ def sweep_fig3():
     return {"sweep": "paper Fig. 3 workloads, AES-128", "rows": rows}
 
 
+# Measured on the box (rocprofv3 --pmc SQ_INSTS_VALU, AES-128 CTR over 4 GiB):
+# VALU lane operations per block of ctr_grouped_kernel.
+CTR_VALU_PER_BLOCK = 207
+
+
+class Roctx:
+    """roctxProfilerPause / Resume from the ROCm profiler SDK, or no-ops when
+    the library is absent."""
+
+    def __init__(self, enabled):
+        import ctypes
+        self.lib = None
+        if enabled:
+            for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
+                try:
+                    self.lib = ctypes.CDLL(name)
+                    break
+                except OSError:
+                    continue
+            if self.lib is None:
+                raise RuntimeError("--roctx-timed: librocprofiler-sdk-roctx.so not found")
+
+    def pause(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerPause(0)
+
+    def resume(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerResume(0)
+
+
+def probes():
+    """On-chip ceilings measured on this GPU (csrc/probe.hip): conflict-free
+    random LDS reads, the T-table round function without HBM traffic, and
+    three-input XOR chains; each with the shader clock it ran at."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_1506_08503_amd", "libaesmi_probe.so")
+    lib = ctypes.CDLL(path)
+    f = lib.aesmi_probe_run
+    f.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_int] + [ctypes.POINTER(ctypes.c_double)] * 3
+    f.restype = ctypes.c_int
+    out = {}
+    for kind, name, iters in ((0, "lds", 40000), (1, "rounds", 10000), (2, "valu", 20000)):
+        ms, rate, clk = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        rc = f(kind, iters, 5, ctypes.byref(ms), ctypes.byref(rate), ctypes.byref(clk))
+        if rc:
+            raise RuntimeError("probe %s failed with HIP error %d" % (name, rc))
+        out[name] = {"rate_t_per_s": round(rate.value / 1e12, 3), "ms": round(ms.value, 3),
+                     "sclk_ghz": round(clk.value, 3)}
+    return out
+
+
+def binding_roofline(lds_reads, nblocks, ms, pr):
+    """The CTR kernel's on-chip position: its LDS reads and VALU operations
+    per second against the probes' measured rates and against the unit peaks
+    at the shader clock the probe held."""
+    sec = ms * 1e-3
+    lds = lds_reads / sec / 1e12
+    valu = CTR_VALU_PER_BLOCK * nblocks / sec / 1e12
+    res = {"lds_treads_per_s": round(lds, 3), "valu_tops_per_s": round(valu, 3),
+           "valu_ops_per_block": CTR_VALU_PER_BLOCK,
+           "valu_ops_per_block_source": "rocprofv3 --pmc SQ_INSTS_VALU x 64 / blocks, "
+                                        "profiles/ctr_grouped_kernel_aes128_ctr_4GiB.md"}
+    if pr:
+        lds_clk, valu_clk = pr["lds"]["sclk_ghz"], pr["valu"]["sclk_ghz"]
+        res.update({
+            "lds_probe_treads_per_s": pr["lds"]["rate_t_per_s"],
+            "lds_frac_of_probe": round(lds / pr["lds"]["rate_t_per_s"], 4),
+            "round_probe_lookups_t_per_s": round(pr["rounds"]["rate_t_per_s"] * 16, 3),
+            "lds_frac_of_round_probe": round(lds / (pr["rounds"]["rate_t_per_s"] * 16), 4),
+            "lds_peak_at_probe_sclk_treads": round(256 * 32 * lds_clk / 1e3, 3),
+            "lds_frac_at_probe_sclk": round(lds / (256 * 32 * lds_clk / 1e3), 4)
+            if lds_clk else None,
+            "valu_probe_tops_per_s": pr["valu"]["rate_t_per_s"],
+            "valu_frac_of_probe": round(valu / pr["valu"]["rate_t_per_s"], 4),
+            "valu_frac_at_probe_sclk": round(valu / (256 * 64 * valu_clk / 1e3), 4)
+            if valu_clk else None,
+            "probes": pr})
+    return res
+
+
 def warm(torch, fn, ms=WARM_MS):
     """Call fn until ms milliseconds have passed (at least three calls) and
     return the number of calls: after idle the chip takes tens of
@@ -331,6 +427,8 @@ def main():
         print("bench.py measures one GPU only: the AES path needs no cross-GPU exchange "
               "and this build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    roctx = Roctx(args.roctx_timed)
+    roctx.pause()
     import torch
     import paper_1506_08503_amd as am
     from paper_1506_08503_amd import workloads as wl
@@ -347,8 +445,14 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     x = torch.empty(inp.nbytes, dtype=torch.uint8, device=dev)
-    for off, piece in inp.plaintext_chunks():
-        x[off:off + piece.size].copy_(torch.from_numpy(piece))
+    if args.plaintext == "zero":
+        x.zero_()
+    else:
+        for off, piece in inp.plaintext_chunks():
+            x[off:off + piece.size].copy_(torch.from_numpy(piece))
+    if args.key_seed is not None:
+        kin = wl.stream_inputs(args.key_seed, args.nbytes, key_bytes=args.key_bytes)
+        inp.key, inp.nonce = kin.key, kin.nonce
     y = torch.empty_like(x)
     ks = am.key_schedule(inp.key, dev)
     kw = {} if layout == am.LAYOUT_AUTO else {"layout": layout}
@@ -372,6 +476,19 @@ def main():
         else:
             am.ctr_xcrypt(ks, inp.nonce, inp.ctr0, x, out=y, **kw)
 
+    tuned = None
+    if (not args.no_tune and args.mode == "aes" and args.layout == "auto"
+            and not args.ctr_precompute and args.op in ("ctr", "ecb-enc", "ecb-dec")):
+        # autotuned launch shape (after a warm-up, so that the candidates are
+        # timed at the working clock); the timed steps use the winner
+        from paper_1506_08503_amd import autotune
+        warm(torch, step)
+        best, table = autotune.tune_plain(args.op, inp.nbytes, args.key_bytes, cache_path=None,
+                                          x=x, y=y)
+        default_ms = next(ms for cand, ms in table if not cand)
+        tuned = {"chosen": best, "chosen_ms": round(table[0][1], 4),
+                 "library_default_ms": round(default_ms, 4), "candidates": len(table)}
+        kw.update(best)
     if args.warmup >= 0:
         for _ in range(args.warmup):
             step()
@@ -382,6 +499,7 @@ def main():
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
     torch.cuda.synchronize()
+    roctx.resume()
     t0 = time.perf_counter()
     for a, b in ev:
         a.record(stream)
@@ -389,6 +507,7 @@ def main():
         b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    roctx.pause()
     kernel_ms = [a.elapsed_time(b) for a, b in ev]
     avg_ms = sum(kernel_ms) / len(kernel_ms)
     ms_per_step = wall * 1e3 / args.steps
@@ -397,6 +516,7 @@ def main():
     value = inp.nbytes / (ms_per_step * 1e-3) / 1e9
     alg_bytes = 32 * nblocks
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    bitslice = args.layout == "bitslice" or kw.get("layout") == am.LAYOUT_BITSLICE
     kernel_name = {("ctr", False): "ctr_grouped_kernel", ("ctr", True): "ctr_bitslice_kernel",
                    ("ecb-enc", False): "ecb_ttable_kernel<false, 0>",
                    ("ecb-enc", True): "ecb_bitslice_kernel<false>",
@@ -404,29 +524,42 @@ def main():
                    ("ecb-dec", True): "ecb_bitslice_kernel<true>",
                    ("gcm-enc", False): "gcm step (ctr_grouped_kernel + ghash passes)",
                    ("gcm-dec", False): "gcm step (ghash passes + ctr_grouped_kernel)"}[
-                       (args.op, args.layout == "bitslice")]
-    # counters were taken for the default workload only (AES-128 CTR, 4 GiB)
-    if args.op == "ctr" and args.layout != "bitslice" and args.ctr_precompute:
-        kernel_name = "ctr_ttable_kernel<4, %s>" % ("true" if args.ctr_precompute == 1
-                                                    else "false")
+                       (args.op, bitslice)]
+    bpl = kw.get("blocks_per_lane", 0) or 4
+    if args.op == "ctr" and not bitslice and (args.ctr_precompute or bpl != 4):
+        kernel_name = "ctr_ttable_kernel<%d, %s>" % (bpl, "false" if args.ctr_precompute == 2
+                                                     else "true")
     default_cfg = (args.op, args.key_bytes, args.nbytes, args.layout,
                    args.ctr_precompute) == ("ctr", 16, 4 << 30, "auto", 0)
-    traffic = load_traffic(args.traffic_json, kernel_name) if default_cfg else None
+    # counters were taken for the default workload only (AES-128 CTR, 4 GiB)
+    traffic = load_traffic(args.traffic_json, kernel_name) \
+        if default_cfg and kernel_name == "ctr_grouped_kernel" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": kernel_name,
+                "traffic": traffic,
+                "traffic_source": ("not measured in this run: FETCH_SIZE + WRITE_SIZE per "
+                                   "dispatch from two rocprofv3 --pmc runs of this command, "
+                                   "scaled by a plain copy's counters (profiles/traffic.json)")
+                if traffic else None,
+                "kernel": kernel_name,
                 "kernel_ms_avg": round(avg_ms, 4), "kernel_ms_min": round(min(kernel_ms), 4)}
-    if args.layout != "bitslice" and not args.op.startswith("gcm"):
+    pr = None
+    if not args.no_probes and args.mode == "aes":
+        pr = probes()
+    if not bitslice and not args.op.startswith("gcm"):
         # On-chip limit of the table kernels: LDS reads per block -- CTR:
         # 16 (Nr - 2) (rounds 1-2 come from per-thread and per-256-counter
         # group precomputation); ECB: 16 Nr -- against 32 reads/clk/CU.
         nr = {16: 10, 24: 12, 32: 14}[args.key_bytes]
-        per_block = {0: 16 * (nr - 2), 1: 16 * nr - 12, 2: 16 * nr}[args.ctr_precompute] \
+        pre = args.ctr_precompute if bpl == 4 else max(args.ctr_precompute, 1)
+        per_block = {0: 16 * (nr - 2), 1: 16 * nr - 12, 2: 16 * nr}[pre] \
             if args.op == "ctr" else 16 * nr
         lds_reads = per_block * nblocks
         roofline["lds_treads_per_s"] = round(lds_reads / (avg_ms * 1e-3) / 1e12, 3)
         roofline["lds_frac_at_2p4ghz"] = round(lds_reads / (avg_ms * 1e-3) / 1e12
                                                / LDS_PEAK_TREADS, 4)
+        if kernel_name == "ctr_grouped_kernel" and args.key_bytes == 16:
+            roofline["binding"] = binding_roofline(lds_reads, nblocks, avg_ms, pr)
     if args.mode == "copy":
         print(json.dumps({"mode": "copy", "nbytes": inp.nbytes, "ms_avg": round(avg_ms, 4),
                           "GBps_read_plus_write": round(2 * inp.nbytes / (avg_ms * 1e-3) / 1e9,
@@ -445,8 +578,10 @@ def main():
                                                          args.nbytes >> 20),
                       "nbytes": inp.nbytes,
                       "blocks": nblocks, "layout": args.layout, "in_place": False,
-                      "ctr_precompute": args.ctr_precompute},
+                      "ctr_precompute": args.ctr_precompute, "launch": dict(kw)},
            "roofline": roofline}
+    if tuned:
+        out["tune"] = tuned
     if not args.no_gcm and default_cfg:
         out["gcm"] = gcm_leg(am, ks, inp.nonce, x, y)
     del x, y
@@ -455,6 +590,8 @@ def main():
         out["batched"] = batched_leg()
     if not args.no_serving:
         out["serving"] = serving_leg(args.serving_requests)
+    if not args.no_sweep and default_cfg:
+        out["sweep"] = sweep_fig3()
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(inp, threads)

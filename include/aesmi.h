@@ -242,6 +242,11 @@ typedef struct aes_batch_tune {
     uint32_t wg_size;         /* threads per workgroup                         */
     uint32_t grid_per_cu;     /* persistent workgroups per compute unit        */
     uint32_t tile_blocks;     /* 16-byte blocks per tile claimed by a wave     */
+    uint32_t blocks_per_lane; /* table layout: 1, 2 or 4 blocks a lane carries
+                                 at once (default 4, which also enables the
+                                 round-1/2 precomputation over 256-counter
+                                 groups); the bitsliced layout always packs
+                                 32 blocks per lane and ignores it          */
 } aes_batch_tune_t;
 
 /*
@@ -267,7 +272,8 @@ size_t aes_batched_workspace_bytes(uint32_t nsegs);
  * pointer not 16-byte aligned, ws_dev not 256-byte aligned), AES_ERR_CONFIG
  * (workspace too small, or a tune field out of range: layout, wg_size a
  * multiple of 64 up to 1024 (256 bitsliced), grid_per_cu up to 64,
- * tile_blocks a multiple of 64 up to 2^20 (of 2048 bitsliced)).  nsegs == 0
+ * tile_blocks a multiple of 64 up to 2^20 (of 2048 bitsliced),
+ * blocks_per_lane 0, 1, 2 or 4).  nsegs == 0
  * is a no-op that leaves the workspace untouched.
  */
 aes_status_t aes_ctr_xcrypt_batched(const aes_segment_t *segs_dev, uint32_t nsegs,
@@ -314,8 +320,14 @@ aes_status_t aes_batched_graph_destroy(aes_batched_graph_t *graph);
  * requests arrive).  aes_serve_run plays the whole trace and returns when
  * every request is done or rejected:
  *  - requests are admitted in arrival order while the input plus output
- *    bytes of admitted, unfinished requests fit hbm_budget; a request larger
- *    than the whole budget is rejected;
+ *    bytes of admitted, unfinished requests fit hbm_budget and their outputs
+ *    fit the free part of the output area; a request whose input plus output
+ *    exceeds the whole budget, or whose output exceeds the whole output
+ *    area, is rejected;
+ *  - the output area is a ring: a batch's outputs take one contiguous range
+ *    of it, and the range is reused after the batch has completed and been
+ *    handed to the consumer (on_batch), so admission waits on output memory
+ *    that really frees;
  *  - key schedules live in a device cache of nslots rows (LRU among rows no
  *    in-flight batch uses, empty rows first); one batch takes at most
  *    nslots / nstreams of the free rows, so batches can overlap;
@@ -340,20 +352,31 @@ typedef struct aes_serve_request {
     uint32_t reserved;    /* must be 0                                         */
 } aes_serve_request_t;    /* 48 bytes; requests sorted by arrival_s            */
 
+/* Called on the thread that runs aes_serve_run once a batch has completed on
+ * the device, with the batch's requests [first, first + count) (in request
+ * order, contiguous).  Their outputs are at out_dev + out_off[i] and stay
+ * there until the callback returns; after that the range may be reused.  The
+ * callback may read or copy them (synchronously: anything it enqueues must be
+ * complete before it returns) and must not call aes_serve_run. */
+typedef void (*aes_serve_batch_fn)(void *user, uint64_t first, uint64_t count);
+
 typedef struct aes_serve_params {
     uint32_t nslots;          /* key-schedule cache rows, >= 1                 */
     uint32_t nstreams;        /* batches in flight, 1 .. 8                     */
     uint32_t max_batch_reqs;  /* requests per batch, 1 .. 65536                */
     uint32_t realtime;        /* 1: requests arrive at arrival_s; 0: at once   */
-    uint64_t hbm_budget;      /* admission budget in bytes                     */
-    uint64_t max_batch_bytes; /* payload bytes that close a batch              */
+    uint64_t hbm_budget;      /* admission budget in bytes (any value >= 1)    */
+    uint64_t max_batch_bytes; /* payload bytes that close a batch (>= 1)       */
     double   window_s;        /* longest wait of the oldest queued request     */
+    aes_serve_batch_fn on_batch;  /* consumer of completed batches, or NULL    */
+    void    *user;            /* passed to on_batch                            */
 } aes_serve_params_t;
 
 typedef struct aes_serve_stats {
     uint64_t completed, rejected, batches, bytes;
     uint64_t key_hits, key_misses;   /* per request                            */
     uint64_t max_held;               /* peak admitted input + output bytes     */
+    uint64_t max_out_used;           /* peak bytes of the output area in use   */
     uint32_t max_inflight;
     uint32_t reserved;
     double   elapsed_s;
@@ -365,9 +388,12 @@ typedef struct aes_serve_stats {
  *   keys32      host, nkeys x 32 bytes: key i in its first key_len[i] bytes
  *   key_len     host, nkeys bytes: 16, 24 or 32
  *   pool_dev    device input pool of pool_bytes bytes (16-byte aligned)
- *   out_dev     device output area of out_bytes bytes (16-byte aligned); the
- *               outputs of all requests are laid out in it in batch order,
- *               each padded to 16 bytes, and stay there after the call
+ *   out_dev     device output area of out_bytes bytes (16-byte aligned,
+ *               at least 16), used as a ring: request i's output (padded to
+ *               16 bytes) is written at out_dev + out_off[i]; with out_bytes
+ *               at least the sum of all padded outputs nothing is reused and
+ *               every output is still there after the call, otherwise a
+ *               result is only guaranteed until on_batch returns for it
  *   latency_s   host out, nreq: completion minus scheduled arrival (seconds;
  *               +inf for a rejected request)
  *   out_off     host out, nreq: offset of the request's output in out_dev
@@ -377,14 +403,14 @@ typedef struct aes_serve_stats {
  * AES_ERR_KEYLEN (a key_len not 16/24/32), AES_ERR_ALIGN (pool, output or an
  * in_off not 16-aligned), AES_ERR_SEGMENT (a payload outside the pool, a
  * key_id >= nkeys, nbytes == 0, reserved != 0, ctr0 + blocks > 2^32, or
- * arrivals out of order), AES_ERR_CONFIG (parameters out of range, or out_bytes
- * smaller than the sum of the padded payloads); AES_ERR_HIP if a HIP call
- * fails during the run (outputs and latencies are then incomplete).  Unlike
- * the other entry points this one allocates: the device key table, per-stream
- * pinned and device staging, streams and events (set up before the clock
- * starts, freed before it returns).  Blocks the calling thread for the whole
- * run, polling the device; uses the current device.  The pool must not be
- * written while the call runs.
+ * arrivals out of order), AES_ERR_OVERLAP (pool and output area intersect),
+ * AES_ERR_CONFIG (parameters out of range, out_bytes < 16); AES_ERR_HIP if a
+ * HIP call fails during the run (outputs and latencies are then incomplete).
+ * Unlike the other entry points this one allocates: the device key table,
+ * per-stream pinned and device staging, streams and events (set up before
+ * the clock starts, freed before it returns).  Blocks the calling thread for
+ * the whole run, polling the device; uses the current device.  The pool must
+ * not be written while the call runs.
  */
 aes_status_t aes_serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8_t *keys32,
                            const uint8_t *key_len, size_t nkeys, const void *pool_dev,

@@ -61,22 +61,29 @@ class Segment(ctypes.Structure):
 
 class BatchTune(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_uint32), ("wg_size", ctypes.c_uint32),
-                ("grid_per_cu", ctypes.c_uint32), ("tile_blocks", ctypes.c_uint32)]
+                ("grid_per_cu", ctypes.c_uint32), ("tile_blocks", ctypes.c_uint32),
+                ("blocks_per_lane", ctypes.c_uint32)]
+
+
+# void (*)(void *user, uint64_t first, uint64_t count)
+SERVE_BATCH_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64)
 
 
 class ServeParams(ctypes.Structure):
     _fields_ = [("nslots", ctypes.c_uint32), ("nstreams", ctypes.c_uint32),
                 ("max_batch_reqs", ctypes.c_uint32), ("realtime", ctypes.c_uint32),
                 ("hbm_budget", ctypes.c_uint64), ("max_batch_bytes", ctypes.c_uint64),
-                ("window_s", ctypes.c_double)]
+                ("window_s", ctypes.c_double), ("on_batch", SERVE_BATCH_FN),
+                ("user", ctypes.c_void_p)]
 
 
 class ServeStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
                 ("key_hits", ctypes.c_uint64), ("key_misses", ctypes.c_uint64),
-                ("max_held", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("elapsed_s", ctypes.c_double)]
+                ("max_held", ctypes.c_uint64), ("max_out_used", ctypes.c_uint64),
+                ("max_inflight", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("elapsed_s", ctypes.c_double)]
 
 
 SERVE_REQUEST_BYTES = 48
@@ -92,7 +99,7 @@ def serve_request_dtype():
     return dt
 
 
-assert ctypes.sizeof(ServeParams) == 40 and ctypes.sizeof(ServeStats) == 72
+assert ctypes.sizeof(ServeParams) == 56 and ctypes.sizeof(ServeStats) == 80
 assert ctypes.sizeof(KeySchedule) == SCHEDULE_BYTES
 assert ctypes.sizeof(Segment) == SEGMENT_BYTES
 
@@ -427,7 +434,7 @@ def _tune(tune):
     if isinstance(tune, BatchTune):
         return tune
     return BatchTune(tune.get("layout", 0), tune.get("wg_size", 0), tune.get("grid_per_cu", 0),
-                     tune.get("tile_blocks", 0))
+                     tune.get("tile_blocks", 0), tune.get("blocks_per_lane", 0))
 
 
 def ctr_xcrypt_batched(segs: torch.Tensor, ks_table: torch.Tensor, x: torch.Tensor,

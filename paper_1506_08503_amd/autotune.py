@@ -1,12 +1,20 @@
-"""Autotuner for the batched launch: layout, tile size and workgroup shape.
+"""Autotuners for the launch shapes: layout, blocks per lane, tile size and
+workgroup shape.
 
-The persistent batched kernel has four knobs (aes_batch_tune_t): the round
-function layout (LDS tables or bitsliced), tile_blocks (16-byte blocks per tile
-a wave claims), wg_size and grid_per_cu.  ``tune_batched`` times every
+The persistent batched kernel has five knobs (aes_batch_tune_t): the round
+function layout (LDS tables or bitsliced), blocks_per_lane (table layout: 1, 2
+or 4 blocks a lane carries at once), tile_blocks (16-byte blocks per tile a
+wave claims), wg_size and grid_per_cu.  ``tune_batched`` times every
 candidate on the caller's own batch with HIP events and keeps the fastest;
 results are cached in a JSON file keyed by device name and a coarse class of
 the batch (segment count and total bytes, rounded to powers of two), so a
 serving process tunes once per shape class.
+
+The plain ECB / CTR calls take an aes_launch_t (layout, wg_size,
+grid_per_cu, blocks_per_lane); ``tune_plain`` times the candidates for one
+operation, key size and length class on a scratch buffer of that length and
+caches the winner the same way.  The library's own defaults are static rules;
+a caller that tunes passes the result as the launch shape.
 """
 from __future__ import annotations
 
@@ -27,10 +35,11 @@ def candidates(include_bitslice: bool = True) -> list[dict]:
     out = []
     for tile in (256, 512, 1024, 2048, 4096, 8192):
         for wg in (512, 1024):
-            out.append({"layout": aesmi.LAYOUT_TTABLE, "tile_blocks": tile, "wg_size": wg,
-                        "grid_per_cu": 1})
+            for bpl in (4, 2, 1):
+                out.append({"layout": aesmi.LAYOUT_TTABLE, "tile_blocks": tile, "wg_size": wg,
+                            "grid_per_cu": 1, "blocks_per_lane": bpl})
     out.append({"layout": aesmi.LAYOUT_TTABLE, "tile_blocks": 2048, "wg_size": 1024,
-                "grid_per_cu": 2})
+                "grid_per_cu": 2, "blocks_per_lane": 4})
     if include_bitslice:
         for tile in (2048, 4096):
             for wg, gpc in ((256, 2), (128, 4)):
@@ -93,6 +102,71 @@ def tune_batched(dbatch, reps: int = 3, cache_path: str | None = DEFAULT_CACHE,
     for cand in candidates(include_bitslice):
         ms = time_launch(lambda: dbatch.run(cand), reps)
         table.append((cand, ms))
+    table.sort(key=lambda r: r[1])
+    best = table[0][0]
+    if cache_path:
+        cache[key] = {"tune": best, "table": table}
+        _save(cache_path, cache)
+    return best, table
+
+
+def plain_candidates(op: str, include_bitslice: bool = True) -> list[dict]:
+    """Launch shapes for aes_ecb_* / aes_ctr_xcrypt_ex (0 = library default)."""
+    out = [{}]
+    for wg in (256, 512, 1024):
+        for gpc in (0, 1, 2, 4, 8):
+            for bpl in (1, 2, 4):
+                out.append({"layout": aesmi.LAYOUT_TTABLE, "wg_size": wg, "grid_per_cu": gpc,
+                            "blocks_per_lane": bpl})
+    if include_bitslice:
+        for wg in (128, 256):
+            for gpc in (0, 2, 8):
+                out.append({"layout": aesmi.LAYOUT_BITSLICE, "wg_size": wg, "grid_per_cu": gpc})
+    return out
+
+
+def size_class(nbytes: int) -> str:
+    return "bytes2^%d" % max(0, math.ceil(math.log2(max(nbytes, 1))))
+
+
+def tune_plain(op: str, nbytes: int, key_bytes: int = 16, reps: int = 3,
+               cache_path: str | None = DEFAULT_CACHE, include_bitslice: bool = True,
+               force: bool = False, device="cuda", x=None, y=None):
+    """Fastest launch shape for op ("ctr", "ecb-enc" or "ecb-dec") over
+    nbytes with key_bytes-byte keys, timed on a scratch buffer of that
+    length (or on the caller's uint8 device buffers x -> y of nbytes bytes);
+    returns (launch dict, table of (launch, ms))."""
+    if op not in ("ctr", "ecb-enc", "ecb-dec"):
+        raise ValueError("op must be ctr, ecb-enc or ecb-dec")
+    dev = torch.device(device)
+    key = "%s|plain-%s-aes%d|%s" % (torch.cuda.get_device_name(dev), op, 8 * key_bytes,
+                                    size_class(nbytes))
+    cache = _load(cache_path) if cache_path else {}
+    if not force and key in cache:
+        return cache[key]["tune"], cache[key]["table"]
+    nbytes = nbytes // 16 * 16 if op != "ctr" else nbytes
+    if x is None or y is None:
+        g = torch.Generator(device=dev)
+        g.manual_seed(0xA7)
+        x = torch.randint(0, 256, (max(nbytes, 16),), dtype=torch.uint8, device=dev,
+                          generator=g)
+        y = torch.empty_like(x)
+    elif x.numel() < nbytes or y.numel() < nbytes:
+        raise ValueError("x and y must hold nbytes bytes")
+    else:
+        x, y = x[:nbytes], y[:nbytes]
+    ks = aesmi.key_schedule(bytes(range(key_bytes)), dev)
+
+    def call(launch):
+        if op == "ctr":
+            aesmi.ctr_xcrypt(ks, bytes(12), 0, x, out=y, **launch)
+        elif op == "ecb-enc":
+            aesmi.ecb_encrypt(ks, x, out=y, **launch)
+        else:
+            aesmi.ecb_decrypt(ks, x, out=y, **launch)
+    table = []
+    for cand in plain_candidates(op, include_bitslice):
+        table.append((cand, time_launch(lambda: call(cand), reps)))
     table.sort(key=lambda r: r[1])
     best = table[0][0]
     if cache_path:

@@ -3,7 +3,8 @@
     python -m paper_1506_08503_amd.build
 
 Each csrc/*.hip file is compiled to an object under _build/ (in parallel) and
-linked into paper_1506_08503_amd/libaesmi.so.  Always rebuilds.
+linked into paper_1506_08503_amd/libaesmi.so; the benchmark's microbenchmarks
+(csrc/probe.hip) go into libaesmi_probe.so beside it.  Always rebuilds.
 """
 from __future__ import annotations
 
@@ -23,6 +24,9 @@ ARCH = "gfx950"
 
 SOURCES = ["api.hip", "ttable.hip", "bitslice.hip", "keyexp.hip", "batched.hip", "cbc.hip", "gcm.hip",
            "serve.hip"]
+# microbenchmarks of the on-chip ceilings, used by bench.py only
+PROBE_SOURCES = ["probe.hip"]
+PROBE_LIB = os.path.join(PKG, "libaesmi_probe.so")
 
 CFLAGS = ["-std=c++17", "-O3", "-fPIC", "--offload-arch=" + ARCH, "-I" + INCLUDE, "-I" + CSRC,
           "-Wall", "-Wno-unused-function",
@@ -43,16 +47,21 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(min(len(SOURCES), 8)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _link(objs, lib):
+    tmp = lib + ".tmp%d" % os.getpid()
     subprocess.check_call([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp]
                           + objs)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = True) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    with ThreadPoolExecutor(min(len(SOURCES) + len(PROBE_SOURCES), 8)) as ex:
+        objs = list(ex.map(_compile, SOURCES + PROBE_SOURCES))
+    _link(objs[:len(SOURCES)], LIB)
+    _link(objs[len(SOURCES):], PROBE_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", PROBE_LIB)
     return LIB
 
 

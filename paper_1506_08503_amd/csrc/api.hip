@@ -77,6 +77,27 @@ uint32_t layout_of(const aes_launch_t *launch)
     return launch ? launch->layout : (uint32_t)AES_LAYOUT_AUTO;
 }
 
+bool valid_batch_tune(const aes_batch_tune_t *tune)
+{
+    if (!tune)
+        return true;
+    if (tune->layout > AES_LAYOUT_BITSLICE)
+        return false;
+    if (tune->wg_size && (tune->wg_size % 64 || tune->wg_size > 1024))
+        return false;
+    if (tune->grid_per_cu > 64)
+        return false;
+    if (tune->tile_blocks && (tune->tile_blocks % 64 || tune->tile_blocks > (1u << 20)))
+        return false;
+    if (tune->blocks_per_lane && tune->blocks_per_lane != 1 && tune->blocks_per_lane != 2 &&
+        tune->blocks_per_lane != 4)
+        return false;
+    if (tune->layout == AES_LAYOUT_BITSLICE &&
+        (tune->wg_size > 256 || (tune->tile_blocks && tune->tile_blocks % 2048)))
+        return false;
+    return true;
+}
+
 bool valid_launch(const aes_launch_t *launch)
 {
     if (!launch)
@@ -337,19 +358,8 @@ aes_status_t aes_ctr_xcrypt_batched(const aes_segment_t *segs_dev, uint32_t nseg
         return AES_ERR_ALIGN;
     if (ws_bytes < batched_workspace_bytes(nsegs))
         return AES_ERR_CONFIG;
-    if (tune) {
-        if (tune->layout > AES_LAYOUT_BITSLICE)
-            return AES_ERR_CONFIG;
-        if (tune->wg_size && (tune->wg_size % 64 || tune->wg_size > 1024))
-            return AES_ERR_CONFIG;
-        if (tune->grid_per_cu > 64)
-            return AES_ERR_CONFIG;
-        if (tune->tile_blocks && (tune->tile_blocks % 64 || tune->tile_blocks > (1u << 20)))
-            return AES_ERR_CONFIG;
-        if (tune->layout == AES_LAYOUT_BITSLICE &&
-            (tune->wg_size > 256 || (tune->tile_blocks && tune->tile_blocks % 2048)))
-            return AES_ERR_CONFIG;
-    }
+    if (!valid_batch_tune(tune))
+        return AES_ERR_CONFIG;
     return from_hip(batched_ctr(segs_dev, nsegs, ks_table_dev, nkeys, in_base_dev,
                                 out_base_dev, tune, ws_dev, static_cast<hipStream_t>(stream)));
 }
@@ -471,7 +481,8 @@ aes_status_t aes_serve_run(const aes_serve_request_t *reqs, size_t nreq, const u
                     o0 = reinterpret_cast<uintptr_t>(out_dev);
     if (p0 < o0 + out_bytes && o0 < p0 + pool_bytes)
         return AES_ERR_OVERLAP;
-    uint64_t out_need = 0;
+    if (out_bytes < 16)
+        return AES_ERR_CONFIG;
     for (size_t i = 0; i < nreq; ++i) {
         const aes_serve_request_t &r = reqs[i];
         if (r.in_off & 15u)
@@ -482,12 +493,9 @@ aes_status_t aes_serve_run(const aes_serve_request_t *reqs, size_t nreq, const u
             (uint64_t)r.ctr0 + nblk > (1ull << 32) || !(r.arrival_s >= 0.0) ||
             !(r.arrival_s < 1e18) || (i && r.arrival_s < reqs[i - 1].arrival_s))
             return AES_ERR_SEGMENT;
-        out_need += nblk * 16u;
     }
-    if (out_need > out_bytes)
-        return AES_ERR_CONFIG;
     return serve_run(reqs, nreq, keys32, key_len, nkeys, static_cast<const uint8_t *>(pool_dev),
-                     static_cast<uint8_t *>(out_dev), pr, latency_s, out_off, stats);
+                     static_cast<uint8_t *>(out_dev), out_bytes, pr, latency_s, out_off, stats);
 }
 
 const char *aes_status_string(aes_status_t status)

@@ -258,10 +258,12 @@ __device__ __forceinline__ TileJob make_job(const aes_segment_t *__restrict__ se
     return j;
 }
 
-// Blocks [b0, b1) of one message on one wave with the table kernel: whole
-// 256-counter groups with the round-1/2 precomputation when the counters are
-// group aligned, four blocks per lane otherwise, then the rest one per lane.
-template <int NR>
+// Blocks [b0, b1) of one message on one wave with the table kernel.  With
+// four blocks per lane: whole 256-counter groups with the round-1/2
+// precomputation when the counters are group aligned, four blocks per lane
+// otherwise; with two or one: that many blocks per lane and the round-1
+// terms of the nonce columns only.  Then the rest one block per lane.
+template <int NR, int BPL>
 __device__ void ttable_tile(const TileJob &j, const char *lds, const Lc &lc, uint32_t lane)
 {
     const uint32_t *rk = j.ks->rk_enc;
@@ -272,7 +274,7 @@ __device__ void ttable_tile(const TileJob &j, const char *lds, const Lc &lc, uin
                              xor3(TL(1, u0, 1), TL(2, u1, 2), TL(3, u2, 3)) ^ rk[7]};
     const uint64_t hi = min(j.b1, j.nfull);
     uint64_t b = j.b0;
-    if (((j.ctr0 + (uint32_t)b) & 255u) == 0 && b + 256 <= hi) {
+    if (BPL == 4 && ((j.ctr0 + (uint32_t)b) & 255u) == 0 && b + 256 <= hi) {
         uint32_t r2[4][4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -286,9 +288,11 @@ __device__ void ttable_tile(const TileJob &j, const char *lds, const Lc &lc, uin
         ctr_groups<NR>(rk, j.in, j.out, b, j.ctr0 + (uint32_t)b, n, 1, pre, r2, lds, lc, lane);
         b += 256u * n;
     }
-    for (; b + 256 <= hi; b += 256)
-        ctr_blocks<NR, 4>(rk, j.in, j.out, b + lane, 64, j.ctr0, pre[0], pre[1], pre[2], pre[3],
-                          lds, lc);
+    if (BPL > 1) {
+        for (; b + 64u * BPL <= hi; b += 64u * BPL)
+            ctr_blocks<NR, BPL>(rk, j.in, j.out, b + lane, 64, j.ctr0, pre[0], pre[1], pre[2],
+                                pre[3], lds, lc);
+    }
     for (uint64_t i = b + lane; i < hi; i += 64)
         ctr_blocks<NR, 1>(rk, j.in, j.out, i, 0, j.ctr0, pre[0], pre[1], pre[2], pre[3], lds, lc);
     if (j.tail && j.b1 == j.nfull + 1) {
@@ -307,6 +311,7 @@ __device__ void ttable_tile(const TileJob &j, const char *lds, const Lc &lc, uin
     }
 }
 
+template <int BPL>
 __global__ __launch_bounds__(1024) void batched_ttable_kernel(
     const aes_segment_t *__restrict__ segs, uint32_t nsegs,
     const aes_key_schedule_t *__restrict__ ks_table, const uint8_t *in_base,
@@ -326,9 +331,9 @@ __global__ __launch_bounds__(1024) void batched_ttable_kernel(
         const uint32_t s = find_segment(start, nsegs, t, lane);
         const TileJob j = make_job(segs, start, s, t, tile_blocks, ks_table, in_base, out_base);
         switch (j.ks->nr) {
-        case 10: ttable_tile<10>(j, lds, lc, lane); break;
-        case 12: ttable_tile<12>(j, lds, lc, lane); break;
-        case 14: ttable_tile<14>(j, lds, lc, lane); break;
+        case 10: ttable_tile<10, BPL>(j, lds, lc, lane); break;
+        case 12: ttable_tile<12, BPL>(j, lds, lc, lane); break;
+        case 14: ttable_tile<14, BPL>(j, lds, lc, lane); break;
         default: report_bad_schedule(h); break;
         }
     }
@@ -397,7 +402,7 @@ hipError_t batched_ctr_prepared(const aes_segment_t *segs, uint32_t nsegs,
                                 uint8_t *out_base, void *ws, hipStream_t stream)
 {
     const int cu = device_cu_count() > 0 ? device_cu_count() : 256;
-    hipLaunchKernelGGL(batched_ttable_kernel, dim3((uint32_t)cu), dim3(1024), 0, stream, segs,
+    hipLaunchKernelGGL(batched_ttable_kernel<4>, dim3((uint32_t)cu), dim3(1024), 0, stream, segs,
                        nsegs, ks_table, in_base, out_base, ws);
     return hipGetLastError();
 }
@@ -414,6 +419,9 @@ hipError_t batched_ctr(const aes_segment_t *segs, uint32_t nsegs,
     uint32_t wg = tune && tune->wg_size ? tune->wg_size : (bs ? 256u : 1024u);
     uint32_t per_cu = tune && tune->grid_per_cu ? tune->grid_per_cu : (bs ? 2u : 1u);
     uint32_t tile = tune && tune->tile_blocks ? tune->tile_blocks : kBatchedTileBlocks;
+    const uint32_t bpl = tune && tune->blocks_per_lane ? tune->blocks_per_lane : 4u;
+    if (bpl != 1 && bpl != 2 && bpl != 4)
+        return hipErrorInvalidConfiguration;
     if (wg < 64 || wg % 64 || wg > (bs ? 256u : 1024u))
         return hipErrorInvalidConfiguration;
     if (bs && tile % 2048u)
@@ -430,8 +438,14 @@ hipError_t batched_ctr(const aes_segment_t *segs, uint32_t nsegs,
     if (bs)
         hipLaunchKernelGGL(batched_bitslice_kernel, dim3(grid), dim3(wg), 0, stream, segs, nsegs,
                            ks_table, in_base, out_base, ws);
+    else if (bpl == 4)
+        hipLaunchKernelGGL(batched_ttable_kernel<4>, dim3(grid), dim3(wg), 0, stream, segs, nsegs,
+                           ks_table, in_base, out_base, ws);
+    else if (bpl == 2)
+        hipLaunchKernelGGL(batched_ttable_kernel<2>, dim3(grid), dim3(wg), 0, stream, segs, nsegs,
+                           ks_table, in_base, out_base, ws);
     else
-        hipLaunchKernelGGL(batched_ttable_kernel, dim3(grid), dim3(wg), 0, stream, segs, nsegs,
+        hipLaunchKernelGGL(batched_ttable_kernel<1>, dim3(grid), dim3(wg), 0, stream, segs, nsegs,
                            ks_table, in_base, out_base, ws);
     return hipGetLastError();
 }

@@ -65,8 +65,8 @@ constexpr uint32_t kServeMaxStreams = 8;
 constexpr uint32_t kServeMaxBatch = 65536;
 aes_status_t serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8_t *keys32,
                        const uint8_t *key_len, size_t nkeys, const uint8_t *pool, uint8_t *out,
-                       const aes_serve_params_t &pr, double *latency_s, uint64_t *out_off,
-                       aes_serve_stats_t *stats);
+                       uint64_t out_bytes, const aes_serve_params_t &pr, double *latency_s,
+                       uint64_t *out_off, aes_serve_stats_t *stats);
 
 // --- batched persistent kernel (batched.hip) -------------------------------
 size_t batched_workspace_bytes(uint32_t nsegs);
@@ -87,6 +87,7 @@ hipError_t batched_ctr_prepared(const aes_segment_t *segs, uint32_t nsegs,
                                 const aes_key_schedule_t *ks_table, const uint8_t *in_base,
                                 uint8_t *out_base, void *ws, hipStream_t stream);
 constexpr uint32_t kBatchedTileBlocks = 2048;   // default tile of the T-table kernel
+
 
 // Host key expansion into the public struct (api.hip).
 aes_status_t expand_key_host(const uint8_t *key, size_t key_bytes, aes_key_schedule_t *ks);

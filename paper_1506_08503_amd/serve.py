@@ -110,10 +110,11 @@ class KeyCache:
         need = np.cumsum(miss + hit_free)
         return int(np.searchsorted(need, int((self.pins == 0).sum()), "right"))
 
-    def take(self, key_ids: np.ndarray):
+    def take(self, key_ids: np.ndarray, row_cap: int | None = None):
         """max_prefix and acquire in one pass (one sort of the keys): returns
         (k, acquire(key_ids[:k])), k = 0 with None when not even the first
-        request fits."""
+        request fits.  With row_cap, the prefix takes at most that many of
+        the unpinned slots."""
         if key_ids.size == 0:
             return 0, None
         uniq, first = np.unique(key_ids, return_index=True)
@@ -123,7 +124,10 @@ class KeyCache:
         needs = (slot_u < 0) | (self.pins[np.maximum(slot_u, 0)] == 0)
         order = np.argsort(first, kind="stable")
         cum = np.cumsum(needs[order])
-        m = int(np.searchsorted(cum, int((self.pins == 0).sum()), "right"))
+        limit = int((self.pins == 0).sum())
+        if row_cap is not None:
+            limit = min(limit, int(row_cap))
+        m = int(np.searchsorted(cum, limit, "right"))
         if m == 0:
             return 0, None
         if m == uniq.size:
@@ -167,6 +171,61 @@ class KeyCache:
         assert np.all(self.pins >= 0)
 
 
+# ---------------------------------------------------------------- out ring
+class OutRing:
+    """The output area as a ring: batches take contiguous byte ranges in
+    submission order and give them back as they retire, in any order; space
+    is reused once every range before it has been given back.  Ranges are
+    never empty.  Allocation moves forward and goes back to offset 0 only
+    when a range does not fit before the end, so an area as large as all the
+    outputs together is never reused.  (The same rules as the library's
+    loop.)"""
+
+    def __init__(self, cap: int):
+        self.cap = int(cap)
+        self.head = 0
+        self.wrapped = False
+        self.live: deque = deque()      # [off, len, freed] in allocation order
+        self.used = 0
+        self.peak = 0
+
+    def max_alloc(self) -> int:
+        if not self.live:
+            return self.cap
+        tail = self.live[0][0]
+        if self.wrapped:
+            return tail - self.head
+        return max(self.cap - self.head, tail)
+
+    def alloc(self, n: int) -> int:
+        if not self.live:
+            off, self.wrapped = (self.head if self.cap - self.head >= n else 0), False
+        elif not self.wrapped and self.cap - self.head >= n:
+            off = self.head
+        elif not self.wrapped:
+            off, self.wrapped = 0, True
+        else:
+            off = self.head
+        self.head = off + n
+        self.live.append([off, n, False])
+        self.used += n
+        self.peak = max(self.peak, self.used)
+        return off
+
+    def release(self, off: int):
+        for r in self.live:
+            if r[0] == off and not r[2]:
+                r[2] = True
+                self.used -= r[1]
+                break
+        while self.live and self.live[0][2]:
+            self.live.popleft()
+        if not self.live:
+            self.wrapped = False
+        elif self.wrapped and self.live[0][0] < self.head:
+            self.wrapped = False
+
+
 # -------------------------------------------------------------------- batches
 @dataclass
 class Batch:
@@ -177,6 +236,7 @@ class Batch:
     slots: np.ndarray           # distinct key slots pinned
     handle: object = None
     out_off: np.ndarray = None  # output offset of each request in the batch buffer
+    out_base: int = 0           # offset of the batch's range in the output ring
 
 
 class ServedResults:
@@ -217,6 +277,7 @@ class Stats:
     key_misses: int = 0
     max_inflight: int = 0
     max_held: int = 0
+    max_out_used: int = 0
 
     def summary(self, skip: int = 0) -> dict:
         """Counts and rates of the whole run; latency percentiles over the
@@ -238,7 +299,12 @@ class Server:
 
     def __init__(self, executor, key_cache: KeyCache, hbm_budget: int,
                  max_batch_bytes: int = 64 << 20, max_batch_reqs: int = 8192,
-                 window_s: float = 25e-6, clock=time.perf_counter):
+                 window_s: float = 25e-6, clock=time.perf_counter,
+                 out_bytes: int | None = None, row_cap: int | None = None, on_batch=None):
+        """out_bytes: size of the output ring (None: unbounded); row_cap: key
+        cache rows one batch may take (None: all unpinned ones); on_batch(first,
+        count, results): consumer of a completed batch, called before its
+        output range is reused."""
         self.ex = executor
         self.kc = key_cache
         self.budget = hbm_budget
@@ -246,6 +312,9 @@ class Server:
         self.max_batch_reqs = max_batch_reqs
         self.window_s = window_s
         self.clock = clock
+        self.out_bytes = out_bytes
+        self.row_cap = row_cap
+        self.on_batch = on_batch
 
     @staticmethod
     def footprint(size: np.ndarray) -> np.ndarray:
@@ -256,6 +325,9 @@ class Server:
     def run(self, reqs: Requests, realtime: bool = True) -> tuple[Stats, ServedResults]:
         n = len(reqs)
         fp = self.footprint(reqs.size)
+        outsz = (reqs.size + 15) // 16 * 16
+        ring_cap = self.out_bytes if self.out_bytes is not None else int(outsz.sum()) + 16
+        ring = OutRing(ring_cap)
         complete = np.full(n, np.nan)
         admitted = np.full(n, np.nan)
         results = ServedResults(self.ex, n)
@@ -275,14 +347,17 @@ class Server:
                     tdone = self.clock() - t0
                     complete[b.first:b.last] = tdone
                     results.add(b.handle, b.first, b.last)
+                    if self.on_batch is not None:
+                        self.on_batch(b.first, b.last - b.first, results)
                     held -= b.held
                     self.kc.release(b.slots)
+                    ring.release(b.out_base)
                     self.ex.release(b.handle)
                     st.completed += b.last - b.first
                     st.bytes += b.nbytes
                     progressed = True
             # reject what can never fit
-            while qh < arrived and fp[qh] > self.budget:
+            while qh < arrived and (fp[qh] > self.budget or outsz[qh] > ring_cap):
                 st.rejected += 1
                 complete[qh] = np.inf
                 qh += 1
@@ -292,11 +367,11 @@ class Server:
                 oldest_wait = now - reqs.arrival[qh] if realtime else 0.0
                 if (not inflight or queued_bytes >= self.max_batch_bytes
                         or oldest_wait >= self.window_s or arrived == n):
-                    b = self._form_batch(reqs, fp, qh, arrived, held)
+                    b = self._form_batch(reqs, fp, outsz, qh, arrived, held, ring)
                     if b is not None:
                         admitted[b.first:b.last] = self.clock() - t0
                         b.handle = self.ex.submit(reqs, b.first, b.last, b.per_req_slots,
-                                                  b.fills)
+                                                  b.fills, out_base=b.out_base)
                         held += b.held
                         inflight.append(b)
                         st.batches += 1
@@ -311,24 +386,28 @@ class Server:
         st.latency_s = np.where(ok, complete - reqs.arrival, np.inf)
         st.admission_wait_s = np.where(ok, admitted - reqs.arrival, np.inf)
         st.key_hits, st.key_misses = self.kc.hits, self.kc.misses
+        st.max_out_used = ring.peak
         return st, results
 
-    def _form_batch(self, reqs, fp, qh, arrived, held):
-        """Largest FIFO prefix of the queue within the budget and batch limits."""
+    def _form_batch(self, reqs, fp, outsz, qh, arrived, held, ring):
+        """Largest FIFO prefix of the queue within the budget, the free output
+        range, the batch limits and the key cache."""
         room = self.budget - held
         cum_fp = np.cumsum(fp[qh:arrived])
+        cum_out = np.cumsum(outsz[qh:arrived])
         cum_b = np.cumsum(reqs.size[qh:arrived])
         k = int(np.searchsorted(cum_fp, room, "right"))
+        k = min(k, int(np.searchsorted(cum_out, ring.max_alloc(), "right")))
         k = min(k, int(np.searchsorted(cum_b, self.max_batch_bytes, "right")) or 1,
                 self.max_batch_reqs, arrived - qh)
         if k == 0:
             return None
-        k, got = self.kc.take(reqs.key_id[qh:qh + k])
+        k, got = self.kc.take(reqs.key_id[qh:qh + k], self.row_cap)
         if k == 0:
             return None
         per_req, slots, fills = got
         b = Batch(first=qh, last=qh + k, nbytes=int(cum_b[k - 1]), held=int(cum_fp[k - 1]),
-                  slots=slots)
+                  slots=slots, out_base=ring.alloc(int(cum_out[k - 1])))
         b.per_req_slots = per_req
         b.fills = fills
         return b
@@ -439,7 +518,10 @@ class GpuExecutor:
         idx = slot["keys_d"][ipos:ipos + 8 * n].view(torch.int64)
         self.table.index_copy_(0, idx, sched[:n])
 
-    def submit(self, reqs, first, last, key_slots, fills):
+    def submit(self, reqs, first, last, key_slots, fills, out_base=None):
+        """Launch one batch.  Its outputs go to a buffer of the executor's own
+        (carved from the arena while it lasts); out_base, the loop's ring
+        offset, is not used: results stay valid for the executor's life."""
         torch, am = self.torch, self.am
         slot = next(s for s in self.slots if not s["busy"])
         n = last - first
@@ -532,12 +614,16 @@ class NativeResults:
 def run_native(pool, keys: list, reqs: Requests, nslots: int, nstreams: int = 2,
                hbm_budget: int = 4 << 30, max_batch_reqs: int = 8192,
                max_batch_bytes: int = 64 << 20, window_s: float = 25e-6,
-               realtime: bool = True, out=None):
+               realtime: bool = True, out=None, on_batch=None):
     """The same request loop as Server with GpuExecutor, run in the library
     (aes_serve_run): admission, the key-schedule cache, batch formation and
     launches happen in C++ without returning to Python per batch.  Returns
-    (Stats, NativeResults).  `out` (uint8 device tensor) must hold every
-    request's 16-padded output; by default one is allocated."""
+    (Stats, NativeResults).  `out` (uint8 device tensor) is the output ring;
+    by default one that holds every request's 16-padded output, so nothing
+    is reused and every result is still there afterwards.  With a smaller
+    ring, on_batch(first, count, out_off) is called as each batch completes
+    (out_off: the offsets filled so far) and must copy out what it needs
+    before it returns."""
     import torch
     from . import aesmi
     aesmi._dev_u8(pool, "pool")
@@ -558,10 +644,19 @@ def run_native(pool, keys: list, reqs: Requests, nslots: int, nstreams: int = 2,
     if out is None:
         out = torch.empty(max(need, 16), dtype=torch.uint8, device=pool.device)
     aesmi._dev_u8(out, "output area")
-    prm = aesmi.ServeParams(nslots, nstreams, max_batch_reqs, 1 if realtime else 0,
-                            hbm_budget, max_batch_bytes, window_s)
     lat = np.empty(n, np.float64)
     off = np.empty(n, np.uint64)
+    errors = []
+    cb = aesmi.SERVE_BATCH_FN()
+    if on_batch is not None:
+        def _cb(user, first, count):
+            try:
+                on_batch(int(first), int(count), off)
+            except BaseException as e:     # an exception cannot cross the C frame
+                errors.append(e)
+        cb = aesmi.SERVE_BATCH_FN(_cb)
+    prm = aesmi.ServeParams(nslots, nstreams, max_batch_reqs, 1 if realtime else 0,
+                            hbm_budget, max_batch_bytes, window_s, cb, None)
     st = aesmi.ServeStats()
     with torch.cuda.device(pool.device):
         torch.cuda.synchronize(pool.device)
@@ -569,9 +664,11 @@ def run_native(pool, keys: list, reqs: Requests, nslots: int, nstreams: int = 2,
             tab.ctypes.data, n, keys32.ctypes.data, klen.ctypes.data, len(keys),
             pool.data_ptr(), pool.numel(), out.data_ptr(), out.numel(), ctypes.byref(prm),
             lat.ctypes.data, off.ctypes.data, ctypes.byref(st)), "aes_serve_run")
+    if errors:
+        raise errors[0]
     stats = Stats(completed=int(st.completed), rejected=int(st.rejected), bytes=int(st.bytes),
                   batches=int(st.batches), elapsed_s=float(st.elapsed_s), latency_s=lat,
                   admission_wait_s=np.zeros(n), key_hits=int(st.key_hits),
                   key_misses=int(st.key_misses), max_inflight=int(st.max_inflight),
-                  max_held=int(st.max_held))
+                  max_held=int(st.max_held), max_out_used=int(st.max_out_used))
     return stats, NativeResults(out, off, reqs.size)

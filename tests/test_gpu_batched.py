@@ -25,6 +25,10 @@ TUNES = [None,
          {"layout": am.LAYOUT_TTABLE, "tile_blocks": 64, "wg_size": 256, "grid_per_cu": 2},
          {"layout": am.LAYOUT_TTABLE, "tile_blocks": 256, "wg_size": 1024, "grid_per_cu": 1},
          {"layout": am.LAYOUT_TTABLE, "tile_blocks": 4096, "wg_size": 512, "grid_per_cu": 1},
+         {"layout": am.LAYOUT_TTABLE, "tile_blocks": 1024, "wg_size": 1024, "grid_per_cu": 1,
+          "blocks_per_lane": 2},
+         {"layout": am.LAYOUT_TTABLE, "tile_blocks": 512, "wg_size": 256, "grid_per_cu": 4,
+          "blocks_per_lane": 1},
          {"layout": am.LAYOUT_BITSLICE, "tile_blocks": 2048, "wg_size": 256, "grid_per_cu": 2},
          {"layout": am.LAYOUT_BITSLICE, "tile_blocks": 4096, "wg_size": 64, "grid_per_cu": 4}]
 
@@ -98,9 +102,14 @@ def run_case(case, tune, in_place=False):
     return out.cpu().numpy(), ws
 
 
-@pytest.mark.parametrize("tune", TUNES, ids=lambda t: "default" if t is None else
-                         "%s-t%d-w%d-g%d" % ("bs" if t["layout"] == 2 else "tt", t["tile_blocks"],
-                                             t["wg_size"], t["grid_per_cu"]))
+def _tune_id(t):
+    if t is None:
+        return "default"
+    return "%s-t%d-w%d-g%d-b%d" % ("bs" if t["layout"] == 2 else "tt", t["tile_blocks"],
+                                  t["wg_size"], t["grid_per_cu"], t.get("blocks_per_lane", 0))
+
+
+@pytest.mark.parametrize("tune", TUNES, ids=_tune_id)
 def test_batched_mixed_matches_oracle(mixed, tune):
     out, _ = run_case(mixed, tune)
     off = mixed["out_off"]

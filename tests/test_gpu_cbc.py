@@ -133,3 +133,30 @@ def test_cbc_encrypt_quad_threshold(oracle, nmsg):
     for r in sorted(rows):
         assert np.array_equal(ct[r], oracle.cbc_encrypt(key, ivs[r].tobytes(), pt[r])), r
     assert torch.equal(am.cbc_decrypt(ks, iv, ct_d, nmsg), x)
+
+
+def test_cbc_fig3_long_rows_sampled(oracle):
+    """The Fig. 3 length sweep's largest shape: 128 messages of 1 MiB (65,536
+    chained blocks per row) with per-row IVs.  Sixteen rows spread over the
+    matrix (first and last included) equal the oracle's CBC encryption of
+    that row byte for byte; every row decrypts back to its plaintext."""
+    from concurrent.futures import ThreadPoolExecutor
+    g = _rng(0xF1603)
+    key = g.bytes(16)
+    ks = am.key_schedule(key)
+    nmsg, msg_bytes = 128, 1 << 20
+    pt = np.frombuffer(g.bytes(nmsg * msg_bytes), np.uint8).reshape(nmsg, msg_bytes)
+    ivs = np.frombuffer(g.bytes(16 * nmsg), np.uint8).reshape(nmsg, 16)
+    x = torch.from_numpy(pt.copy()).to(DEV).view(-1)
+    iv = torch.from_numpy(ivs.copy()).to(DEV).view(-1)
+    ct_d = am.cbc_encrypt(ks, iv, x, nmsg)
+    ct = ct_d.cpu().numpy().reshape(nmsg, msg_bytes)
+    rows = sorted(set(np.linspace(0, nmsg - 1, 16).astype(int).tolist()))
+
+    def row_ok(r):
+        return np.array_equal(ct[r], oracle.cbc_encrypt(key, ivs[r].tobytes(), pt[r]))
+    with ThreadPoolExecutor(16) as ex:
+        bad = [r for r, ok in zip(rows, ex.map(row_ok, rows)) if not ok]
+    assert not bad, bad
+    back = am.cbc_decrypt(ks, iv, ct_d, nmsg)
+    assert torch.equal(back, x)

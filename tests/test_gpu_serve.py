@@ -129,6 +129,8 @@ def test_native_batch_sizes_cover_every_tile(oracle, max_batch_mib):
     torch.cuda.synchronize()
     assert st.completed == nreq and st.rejected == 0
     assert st.batches >= int(reqs.size.sum()) // ((max_batch_mib + 2) << 20)
+    # backlogged on two streams: a second batch was launched while the first ran
+    assert st.max_inflight == 2
     for i in range(nreq):
         a, n = int(reqs.in_off[i]), int(reqs.size[i])
         ks = am.key_schedule(rs.keys[reqs.key_id[i]], DEV)
@@ -170,3 +172,61 @@ def test_native_all_key_sizes(oracle):
         exp = oracle.ctr_xcrypt(rs.keys[reqs.key_id[i]], reqs.nonce[i].tobytes(),
                                 int(reqs.ctr0[i]), pool_h[a:a + n])
         assert np.array_equal(res[i].cpu().numpy(), exp), i
+
+
+@pytest.mark.parametrize("realtime", [False, True])
+def test_native_small_output_ring(oracle, realtime):
+    """The output area is a quarter of the trace's output: batches take ranges
+    of it and give them back when they retire, so later batches reuse the
+    same bytes and admission waits for them.  A consumer copies each
+    completed batch out before its range is reused; every collected result
+    equals the request run alone and the oracle's CTR, two batches were in
+    flight at once, and the ring never held more than its size."""
+    nreq, pool_bytes = 2500, 32 << 20
+    rs = wl.serving_inputs(nreq, 4e5, nkeys=48, median=8192, sigma=1.5, max_size=1 << 20,
+                           seed=61 + realtime)
+    reqs = serve.requests_from_stream(rs, pool_bytes, seed=62)
+    g = np.random.Generator(np.random.PCG64(63))
+    pool_h = np.frombuffer(g.bytes(pool_bytes), np.uint8).copy()
+    pool = torch.from_numpy(pool_h).to(DEV)
+    pad = (reqs.size + 15) // 16 * 16
+    lin = np.concatenate([[0], np.cumsum(pad)])
+    total = int(lin[-1])
+    ring_bytes = (total // 4) // 16 * 16
+    assert ring_bytes >= int(pad.max())
+    out = torch.full((ring_bytes,), 0xEE, dtype=torch.uint8, device=DEV)
+    collected = torch.zeros(total, dtype=torch.uint8, device=DEV)
+    seen = np.zeros(nreq, bool)
+
+    def consume(first, count, out_off):
+        # the batch's outputs are contiguous in the ring, in request order
+        o = int(out_off[first])
+        n = int(lin[first + count] - lin[first])
+        assert o + n <= ring_bytes
+        assert not seen[first:first + count].any()
+        seen[first:first + count] = True
+        collected[int(lin[first]):int(lin[first]) + n].copy_(out[o:o + n])
+        torch.cuda.synchronize()
+
+    st, _ = serve.run_native(pool, rs.keys, reqs, nslots=16, nstreams=2, hbm_budget=1 << 30,
+                             max_batch_bytes=ring_bytes // 6, realtime=realtime, out=out,
+                             on_batch=consume)
+    torch.cuda.synchronize()
+    assert st.completed == nreq and st.rejected == 0 and seen.all()
+    assert st.max_out_used <= ring_bytes and st.max_inflight == 2
+    assert st.bytes == int(reqs.size.sum()) and total > 3 * ring_bytes
+    col = collected.cpu().numpy()
+    for i in range(nreq):
+        a, n = int(reqs.in_off[i]), int(reqs.size[i])
+        ks = am.key_schedule(rs.keys[reqs.key_id[i]], DEV)
+        alone = am.ctr_xcrypt(ks, reqs.nonce[i].tobytes(), int(reqs.ctr0[i]), pool[a:a + n])
+        assert np.array_equal(col[int(lin[i]):int(lin[i]) + n], alone.cpu().numpy()), i
+
+    def agrees(i):
+        a, n = int(reqs.in_off[i]), int(reqs.size[i])
+        exp = oracle.ctr_xcrypt(rs.keys[reqs.key_id[i]], reqs.nonce[i].tobytes(),
+                                int(reqs.ctr0[i]), pool_h[a:a + n])
+        return np.array_equal(col[int(lin[i]):int(lin[i]) + n], exp)
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as pool_ex:
+        bad = [i for i, ok in zip(range(nreq), pool_ex.map(agrees, range(nreq))) if not ok]
+    assert not bad, bad[:10]

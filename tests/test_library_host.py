@@ -142,6 +142,9 @@ def test_batched_validation():
     assert f(segs, 10, kt, 4, a, b, None, ws, need - 1, None) == -9
     bad = am.BatchTune(0, 0, 0, 100)
     assert f(segs, 10, kt, 4, a, b, ctypes.byref(bad), ws, need, None) == -9
+    for bpl in (3, 8):
+        bad = am.BatchTune(am.LAYOUT_TTABLE, 0, 0, 0, bpl)
+        assert f(segs, 10, kt, 4, a, b, ctypes.byref(bad), ws, need, None) == -9
     # the bitsliced layout: at most 256 threads, tiles of whole 2048-block batches
     for bad in (am.BatchTune(am.LAYOUT_BITSLICE, 512, 0, 0),
                 am.BatchTune(am.LAYOUT_BITSLICE, 0, 0, 1024)):
@@ -269,4 +272,6 @@ def test_serve_run_validation():
     r = reqs.copy()
     r["ctr0"][2] = 2 ** 32 - 10                             # 256 blocks from 2^32 - 10
     assert call(r=r) == -7
-    assert call(ob=16 + 112 + 4096 - 16) == -9               # one byte block short
+    # the output area is a ring: any size from 16 bytes up is accepted (a
+    # request whose output is larger than the whole area is rejected in the run)
+    assert call(ob=15) == -9

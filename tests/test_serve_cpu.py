@@ -42,7 +42,7 @@ class OracleExecutor:
     def free_slots(self):
         return self.nstreams - self.busy
 
-    def submit(self, reqs, first, last, key_slots, fills):
+    def submit(self, reqs, first, last, key_slots, fills, out_base=None):
         self.busy += 1
         for sl, kid in fills:
             self.resident[sl] = kid
