@@ -15,7 +15,9 @@
  *    a hipStream_t passed as void* (NULL = the null stream).
  *  - The caller owns every buffer.  No entry point allocates device memory,
  *    except that aes_batched_graph_create builds a HIP graph (set-up code)
- *    and aes_serve_run sets up its key cache and staging for a whole run.
+ *    and aes_serve_run sets up its key cache and staging for a whole run;
+ *    aes_ctr_xcrypt_batched_noalloc works in a static workspace of the
+ *    library's own instead of a caller's.
  *  - Launching entry points are stream-ordered and asynchronous: AES_OK means
  *    the arguments passed validation and the work was enqueued on `stream`.
  *    Argument errors are returned before any HIP call is made.
@@ -286,6 +288,30 @@ aes_status_t aes_ctr_xcrypt_batched(const aes_segment_t *segs_dev, uint32_t nseg
  * `stream`; call after the batched launch). */
 aes_status_t aes_batched_read_status(const void *ws_dev, void *stream,
                                      int32_t *status_out);
+
+/*
+ * aes_ctr_xcrypt_batched_noalloc -- aes_ctr_xcrypt_batched without a caller
+ * workspace, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, hosts that forbid allocation).  The
+ * workspace is a static array inside the library, one per device, of fixed
+ * size: nsegs may be at most 65,536.  The call allocates nothing (no
+ * hipMalloc, no pinned memory, no library routine that allocates).
+ *   status_dev  device int32 (4-byte aligned) that receives the segment
+ *               status word (AES_OK or AES_ERR_SEGMENT) once the launch has
+ *               run, or NULL when the caller does not want it
+ * Other arguments, results and errors as aes_ctr_xcrypt_batched, plus
+ * AES_ERR_CONFIG for nsegs > 65,536.  Every call on one device shares that
+ * device's static workspace and keeps it after the call: calls that overlap
+ * on one device (on different streams, or from different threads without
+ * ordering) race and must not be issued; calls ordered on one stream are
+ * fine.  nsegs == 0 is a no-op that leaves *status_dev untouched.
+ */
+aes_status_t aes_ctr_xcrypt_batched_noalloc(const aes_segment_t *segs_dev, uint32_t nsegs,
+                                            const aes_key_schedule_t *ks_table_dev,
+                                            uint32_t nkeys, const uint8_t *in_base_dev,
+                                            uint8_t *out_base_dev,
+                                            const aes_batch_tune_t *tune, int32_t *status_dev,
+                                            void *stream);
 
 /*
  * Graph form of the batched call: captures aes_ctr_xcrypt_batched with fixed

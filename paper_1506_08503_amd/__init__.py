@@ -15,7 +15,8 @@ from .aesmi import (AesError, KeySchedule, Launch, Segment, BatchTune, lib, expa
                     gcm_workspace_bytes, ghash_workspace_bytes, device_cu_count, header_functions,
                     LAYOUT_AUTO, LAYOUT_TTABLE, LAYOUT_BITSLICE, SCHEDULE_BYTES,
                     SEGMENT_BYTES, STATUS, segment_dtype, batched_workspace_bytes,
-                    ctr_xcrypt_batched, batched_read_status, BatchedGraph, ServeParams, ServeStats,
+                    ctr_xcrypt_batched, ctr_xcrypt_batched_noalloc, NOALLOC_MAX_SEGS,
+                    batched_read_status, BatchedGraph, ServeParams, ServeStats,
                     serve_request_dtype)
 
 __all__ = ["AesError", "KeySchedule", "Launch", "Segment", "BatchTune", "lib", "expand_key",
@@ -24,5 +25,6 @@ __all__ = ["AesError", "KeySchedule", "Launch", "Segment", "BatchTune", "lib", "
            "ghash", "gcm_workspace_bytes", "ghash_workspace_bytes", "device_cu_count", "header_functions",
            "LAYOUT_AUTO", "LAYOUT_TTABLE", "LAYOUT_BITSLICE", "SCHEDULE_BYTES",
            "SEGMENT_BYTES", "STATUS", "segment_dtype", "batched_workspace_bytes",
-           "ctr_xcrypt_batched", "batched_read_status", "BatchedGraph", "ServeParams", "ServeStats",
+           "ctr_xcrypt_batched", "ctr_xcrypt_batched_noalloc", "NOALLOC_MAX_SEGS",
+           "batched_read_status", "BatchedGraph", "ServeParams", "ServeStats",
            "serve_request_dtype"]

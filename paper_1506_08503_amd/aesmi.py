@@ -143,6 +143,8 @@ def lib():
             "aes_ctr_xcrypt_batched": ([vp, u32, vp, u32, vp, vp, ctypes.POINTER(BatchTune),
                                         vp, sz, vp], st),
             "aes_batched_read_status": ([vp, vp, ctypes.POINTER(i32)], st),
+            "aes_ctr_xcrypt_batched_noalloc": ([vp, u32, vp, u32, vp, vp,
+                                                ctypes.POINTER(BatchTune), vp, vp], st),
             "aes_batched_graph_create": ([vp, u32, vp, u32, vp, vp, ctypes.POINTER(BatchTune),
                                           vp, sz, vp, ctypes.POINTER(vp)], st),
             "aes_batched_graph_launch": ([vp, vp], st),
@@ -456,6 +458,33 @@ def ctr_xcrypt_batched(segs: torch.Tensor, ks_table: torch.Tensor, x: torch.Tens
                                           _ptr(out), ctypes.byref(tn) if tn else None, _ptr(ws),
                                           ws.numel(), _stream(x))
     _check(st, "aes_ctr_xcrypt_batched")
+    return out
+
+
+NOALLOC_MAX_SEGS = 65536
+
+
+def ctr_xcrypt_batched_noalloc(segs: torch.Tensor, ks_table: torch.Tensor, x: torch.Tensor,
+                               out: torch.Tensor, tune=None,
+                               status: torch.Tensor | None = None) -> torch.Tensor:
+    """aes_ctr_xcrypt_batched_noalloc: the batched call on the library's static
+    device workspace (at most NOALLOC_MAX_SEGS segments); `status`, an int32
+    CUDA tensor of one element, receives the segment status word."""
+    for t, n in ((segs, "segments"), (ks_table, "key table"), (x, "input"), (out, "output")):
+        _dev_u8(t, n)
+    if status is not None and (not status.is_cuda or status.dtype != torch.int32
+                               or status.numel() < 1):
+        raise ValueError("status must be an int32 CUDA tensor")
+    if segs.numel() % SEGMENT_BYTES or ks_table.numel() % SCHEDULE_BYTES:
+        raise ValueError("segment / key table sizes must be whole records")
+    tn = _tune(tune)
+    with torch.cuda.device(x.device):
+        st = lib().aes_ctr_xcrypt_batched_noalloc(
+            _ptr(segs), segs.numel() // SEGMENT_BYTES, _ptr(ks_table),
+            ks_table.numel() // SCHEDULE_BYTES, _ptr(x), _ptr(out),
+            ctypes.byref(tn) if tn else None,
+            ctypes.c_void_p(status.data_ptr()) if status is not None else None, _stream(x))
+    _check(st, "aes_ctr_xcrypt_batched_noalloc")
     return out
 
 

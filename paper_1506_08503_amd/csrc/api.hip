@@ -379,6 +379,28 @@ aes_status_t aes_batched_read_status(const void *ws_dev, void *stream, int32_t *
     return AES_OK;
 }
 
+aes_status_t aes_ctr_xcrypt_batched_noalloc(const aes_segment_t *segs_dev, uint32_t nsegs,
+                                            const aes_key_schedule_t *ks_table_dev,
+                                            uint32_t nkeys, const uint8_t *in_base_dev,
+                                            uint8_t *out_base_dev, const aes_batch_tune_t *tune,
+                                            int32_t *status_dev, void *stream)
+{
+    if (nsegs == 0)
+        return AES_OK;
+    if (!segs_dev || !ks_table_dev || !in_base_dev || !out_base_dev)
+        return AES_ERR_NULL;
+    if (nkeys == 0)
+        return AES_ERR_SEGMENT;
+    if (!aligned16(in_base_dev) || !aligned16(out_base_dev) || !aligned16(segs_dev) ||
+        (reinterpret_cast<uintptr_t>(status_dev) & 3u))
+        return AES_ERR_ALIGN;
+    if (nsegs > batched_noalloc_max_segs() || !valid_batch_tune(tune))
+        return AES_ERR_CONFIG;
+    return from_hip(batched_ctr_noalloc(segs_dev, nsegs, ks_table_dev, nkeys, in_base_dev,
+                                        out_base_dev, tune, status_dev,
+                                        static_cast<hipStream_t>(stream)));
+}
+
 struct aes_batched_graph {
     hipGraph_t graph;
     hipGraphExec_t exec;

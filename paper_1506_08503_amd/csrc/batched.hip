@@ -28,6 +28,20 @@
 #include "internal.hpp"
 #include "ttable_dev.hpp"
 
+#include <mutex>
+
+// Workspace of the allocation-free batched call (aes_ctr_xcrypt_batched_noalloc):
+// the header line, the 16 claim-counter lines and tile_start[0..nsegs] for up
+// to 65,536 segments, 261 KiB.  Each device holds its own copy from the time
+// the library's code object is loaded there until the process ends.  Host
+// code never passes this name to a kernel (on the host it is a stand-in, not
+// a device address): it takes the device address from hipGetSymbolAddress
+// once per device and uses that.
+constexpr uint32_t kNoAllocMaxSegs = 65536;
+constexpr size_t kScratchBytes =
+    (256u * 17u + 4u * ((size_t)kNoAllocMaxSegs + 1u) + 255u) & ~(size_t)255u;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace aesmi {
 namespace {
 
@@ -447,6 +461,64 @@ hipError_t batched_ctr(const aes_segment_t *segs, uint32_t nsegs,
     else
         hipLaunchKernelGGL(batched_ttable_kernel<1>, dim3(grid), dim3(wg), 0, stream, segs, nsegs,
                            ks_table, in_base, out_base, ws);
+    return hipGetLastError();
+}
+
+namespace {
+
+// Copies the status word of a finished batched launch to caller memory.
+__global__ void batched_status_copy(const void *ws, int32_t *status)
+{
+    if (threadIdx.x == 0)
+        *status = static_cast<const WsHeader *>(ws)->status;
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+hipError_t scratch_address(void **out)
+{
+    static std::mutex mu;
+    static void *addr[64];
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= 64)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        if (!p)
+            return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+uint32_t batched_noalloc_max_segs() { return kNoAllocMaxSegs; }
+
+hipError_t batched_ctr_noalloc(const aes_segment_t *segs, uint32_t nsegs,
+                               const aes_key_schedule_t *ks_table, uint32_t nkeys,
+                               const uint8_t *in_base, uint8_t *out_base,
+                               const aes_batch_tune_t *tune, int32_t *status, hipStream_t stream)
+{
+    if (nsegs > kNoAllocMaxSegs || batched_workspace_bytes(nsegs) > kScratchBytes)
+        return hipErrorInvalidValue;
+    void *ws = nullptr;
+    hipError_t e = scratch_address(&ws);
+    if (e != hipSuccess)
+        return e;
+    // the prepare kernel clears the claim counters and the status word
+    e = batched_ctr(segs, nsegs, ks_table, nkeys, in_base, out_base, tune, ws, stream);
+    if (e != hipSuccess || !status)
+        return e;
+    hipLaunchKernelGGL(batched_status_copy, dim3(1), dim3(64), 0, stream, ws, status);
     return hipGetLastError();
 }
 

@@ -88,6 +88,14 @@ hipError_t batched_ctr_prepared(const aes_segment_t *segs, uint32_t nsegs,
                                 uint8_t *out_base, void *ws, hipStream_t stream);
 constexpr uint32_t kBatchedTileBlocks = 2048;   // default tile of the T-table kernel
 
+// The batched call on the library's own static device workspace (no
+// allocation); at most batched_noalloc_max_segs() segments.  When status is
+// not NULL the segment status word is copied there after the launch.
+uint32_t batched_noalloc_max_segs();
+hipError_t batched_ctr_noalloc(const aes_segment_t *segs, uint32_t nsegs,
+                               const aes_key_schedule_t *ks_table, uint32_t nkeys,
+                               const uint8_t *in_base, uint8_t *out_base,
+                               const aes_batch_tune_t *tune, int32_t *status, hipStream_t stream);
 
 // Host key expansion into the public struct (api.hip).
 aes_status_t expand_key_host(const uint8_t *key, size_t key_bytes, aes_key_schedule_t *ks);

@@ -157,6 +157,23 @@ def test_batched_validation():
     assert L.aes_batched_graph_launch(None, None) == -1
 
 
+def test_batched_noalloc_validation():
+    """The allocation-free batched call checks its arguments before any HIP
+    call: more segments than its static workspace holds, a bad tune or a
+    misaligned status pointer are refused."""
+    segs, kt, a, b, stp = VP(0x10000), VP(0x20000), VP(0x40000), VP(0x80000), VP(0x100000)
+    f = L.aes_ctr_xcrypt_batched_noalloc
+    assert am.NOALLOC_MAX_SEGS == 65536
+    assert f(None, 0, None, 0, None, None, None, None, None) == 0
+    assert f(None, 10, kt, 4, a, b, None, stp, None) == -1
+    assert f(segs, 10, kt, 0, a, b, None, stp, None) == -7
+    assert f(segs, 10, kt, 4, VP(0x40008), b, None, stp, None) == -4
+    assert f(segs, 10, kt, 4, a, b, None, VP(0x100002), None) == -4
+    assert f(segs, 65537, kt, 4, a, b, None, stp, None) == -9
+    bad = am.BatchTune(am.LAYOUT_TTABLE, 0, 0, 0, 3)
+    assert f(segs, 10, kt, 4, a, b, ctypes.byref(bad), stp, None) == -9
+
+
 def test_binding_rejects_cpu_tensors():
     import torch
     x = torch.zeros(32, dtype=torch.uint8)
@@ -275,3 +292,4 @@ def test_serve_run_validation():
     # the output area is a ring: any size from 16 bytes up is accepted (a
     # request whose output is larger than the whole area is rejected in the run)
     assert call(ob=15) == -9
+
