@@ -77,9 +77,16 @@ def parse():
                    help="time the library's default launch shape instead of the autotuned one")
     p.add_argument("--no-probes", action="store_true",
                    help="leave out the on-chip ceiling microbenchmarks (LDS, rounds, VALU)")
-    p.add_argument("--roctx-timed", action="store_true",
-                   help="pause the profiler (roctx) except around the timed steps: with "
-                        "rocprofv3 --selected-regions only those steps are traced")
+    p.add_argument("--trace-summary", metavar="DIR",
+                   help="instead of the benchmark: summarize the kernel trace that "
+                        "rocprofv3 --kernel-trace --output-format csv wrote under DIR, over "
+                        "the last --last dispatches of each kernel (the timed steps of a "
+                        "bench run are its last dispatches of the stream kernel)")
+    p.add_argument("--pmc-summary", metavar="DIR",
+                   help="instead of the benchmark: average the counters rocprofv3 --pmc "
+                        "--output-format csv wrote under DIR over the last --last dispatches "
+                        "of each kernel")
+    p.add_argument("--last", type=int, default=20)
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     return p.parse_args()
 
@@ -114,8 +121,10 @@ def cpu_baseline(inp, threads):
 
 def batched_leg():
     """10,000 messages (log-uniform 1 B .. 1 MiB, own AES-128 key and nonce):
-    one persistent launch (autotuned, replayed as a HIP graph) against a loop
-    of one plain aes_ctr_xcrypt launch per message."""
+    one persistent launch (autotuned; replayed as a HIP graph, and called
+    directly, each 20 times back to back) against a loop of one plain
+    aes_ctr_xcrypt launch per message.  GBps_batched is the faster of the
+    two forms, named in `form`."""
     import torch
     from paper_1506_08503_amd import autotune, batch, workloads as wl
     b = wl.batched_inputs()
@@ -136,6 +145,16 @@ def batched_leg():
     e.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(e) / reps
+    # the same launch without the graph, back to back
+    db.run(tune)
+    torch.cuda.synchronize()
+    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        db.run(tune)
+    e.record()
+    torch.cuda.synchronize()
+    ms_direct = a.elapsed_time(e) / reps
     torch.cuda.synchronize()
     a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -146,9 +165,14 @@ def batched_leg():
     wall = (time.perf_counter() - t0) * 1e3
     loop_ms = a.elapsed_time(e)
     g.close()
+    best, form = (ms, "graph") if ms <= ms_direct else (ms_direct, "direct")
     return {"workload": "10000 messages, log-uniform 1 B..1 MiB, own AES-128 key+nonce",
-            "bytes": db.nbytes, "GBps_batched": round(db.nbytes / ms / 1e6, 1),
-            "ms_batched_graph": round(ms, 4), "ms_batched_graph_single_call": round(ms_single, 4),
+            "bytes": db.nbytes, "GBps_batched": round(db.nbytes / best / 1e6, 1),
+            "form": form,
+            "GBps_batched_graph": round(db.nbytes / ms / 1e6, 1),
+            "GBps_batched_direct": round(db.nbytes / ms_direct / 1e6, 1),
+            "ms_batched_graph": round(ms, 4), "ms_batched_direct": round(ms_direct, 4),
+            "ms_batched_graph_single_call": round(ms_single, 4),
             "ms_batched_default_tune_single_call": round(ms_default, 4),
             "GBps_plain_loop": round(db.nbytes / loop_ms / 1e6, 2),
             "ms_plain_loop": round(loop_ms, 3), "ms_plain_loop_wall": round(wall, 3),
@@ -279,32 +303,6 @@ def sweep_fig3():
 CTR_VALU_PER_BLOCK = 207
 
 
-class Roctx:
-    """roctxProfilerPause / Resume from the ROCm profiler SDK, or no-ops when
-    the library is absent."""
-
-    def __init__(self, enabled):
-        import ctypes
-        self.lib = None
-        if enabled:
-            for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
-                try:
-                    self.lib = ctypes.CDLL(name)
-                    break
-                except OSError:
-                    continue
-            if self.lib is None:
-                raise RuntimeError("--roctx-timed: librocprofiler-sdk-roctx.so not found")
-
-    def pause(self):
-        if self.lib is not None:
-            self.lib.roctxProfilerPause(0)
-
-    def resume(self):
-        if self.lib is not None:
-            self.lib.roctxProfilerResume(0)
-
-
 def probes():
     """On-chip ceilings measured on this GPU (csrc/probe.hip): conflict-free
     random LDS reads, the T-table round function without HBM traffic, and
@@ -353,6 +351,65 @@ def binding_roofline(lds_reads, nblocks, ms, pr):
             if valu_clk else None,
             "probes": pr})
     return res
+
+
+def trace_summary(root, last):
+    """Per kernel: calls in the trace, and count / average / min / max
+    duration (ms) of its last `last` dispatches, from rocprofv3's kernel
+    trace CSV files under root."""
+    import csv
+    import glob
+    rows = {}
+    for path in sorted(glob.glob(os.path.join(root, "**", "*kernel_trace.csv"), recursive=True)):
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                name = r["Kernel_Name"]
+                rows.setdefault(name, []).append(
+                    (int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    out = {}
+    for name, ts in rows.items():
+        ts.sort()
+        tail = [(e - b) / 1e6 for b, e in ts[-last:]]
+        out[name] = {"calls": len(ts), "last": len(tail),
+                     "avg_ms": round(sum(tail) / len(tail), 4), "min_ms": round(min(tail), 4),
+                     "max_ms": round(max(tail), 4)}
+    return out
+
+
+def pmc_summary(root, last):
+    """Per kernel: the mean of each counter over its last `last` dispatches,
+    from rocprofv3's counter collection CSV files under root, with the mean
+    dispatch duration and, when GRBM_GUI_ACTIVE was collected, the shader
+    clock it implies (the counter is summed over the GPU's XCDs, whose number
+    the agent info file gives)."""
+    import csv
+    import glob
+    per, dur, nxcc = {}, {}, 0
+    for path in sorted(glob.glob(os.path.join(root, "**", "*agent_info.csv"), recursive=True)):
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                if r.get("Agent_Type") == "GPU":
+                    nxcc = int(r["Num_Xcc"])
+    for path in sorted(glob.glob(os.path.join(root, "**", "*counter_collection.csv"),
+                                 recursive=True)):
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                i = int(r["Dispatch_Id"])
+                d = per.setdefault(r["Kernel_Name"], {}).setdefault(i, {})
+                d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+                dur[i] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+    out = {}
+    for name, disp in per.items():
+        ids = sorted(disp)[-last:]
+        keys = sorted({k for i in ids for k in disp[i]})
+        res = {"dispatches": len(disp), "last": len(ids),
+               "duration_ms": round(sum(dur[i] for i in ids) / len(ids), 4),
+               **{k: round(sum(disp[i].get(k, 0.0) for i in ids) / len(ids), 3) for k in keys}}
+        if "GRBM_GUI_ACTIVE" in keys and nxcc:
+            res["sclk_ghz"] = round(sum(disp[i]["GRBM_GUI_ACTIVE"] / nxcc / (dur[i] * 1e6)
+                                        for i in ids) / len(ids), 3)
+        out[name] = res
+    return out
 
 
 def warm(torch, fn, ms=WARM_MS):
@@ -427,8 +484,12 @@ def main():
         print("bench.py measures one GPU only: the AES path needs no cross-GPU exchange "
               "and this build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
-    roctx = Roctx(args.roctx_timed)
-    roctx.pause()
+    if args.trace_summary:
+        print(json.dumps(trace_summary(args.trace_summary, args.last)), flush=True)
+        return
+    if args.pmc_summary:
+        print(json.dumps(pmc_summary(args.pmc_summary, args.last)), flush=True)
+        return
     import torch
     import paper_1506_08503_amd as am
     from paper_1506_08503_amd import workloads as wl
@@ -499,7 +560,6 @@ def main():
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
     torch.cuda.synchronize()
-    roctx.resume()
     t0 = time.perf_counter()
     for a, b in ev:
         a.record(stream)
@@ -507,7 +567,6 @@ def main():
         b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    roctx.pause()
     kernel_ms = [a.elapsed_time(b) for a, b in ev]
     avg_ms = sum(kernel_ms) / len(kernel_ms)
     ms_per_step = wall * 1e3 / args.steps

@@ -167,6 +167,9 @@ def tune_plain(op: str, nbytes: int, key_bytes: int = 16, reps: int = 3,
     table = []
     for cand in plain_candidates(op, include_bitslice):
         table.append((cand, time_launch(lambda: call(cand), reps)))
+    # the library default is timed first, when the clock may still be
+    # settling: time it again last and keep the faster figure
+    table[0] = ({}, min(table[0][1], time_launch(lambda: call({}), reps)))
     table.sort(key=lambda r: r[1])
     best = table[0][0]
     if cache_path:

@@ -82,21 +82,27 @@ __device__ __forceinline__ uint32_t segment_tiles(const aes_segment_t &sg, uint3
         *bad = true;
         return 0;
     }
+    // valid segments have nblk <= 2^32: a 32-bit division unless the rounded
+    // count itself needs 33 bits
+    if (nblk <= 0xffffffffull - tile_blocks)
+        return ((uint32_t)nblk + tile_blocks - 1u) / tile_blocks;
     return (uint32_t)((nblk + tile_blocks - 1) / tile_blocks);
 }
 
 constexpr uint32_t kPrepLdsSegs = 12288;   // tile counts kept in LDS up to this many segments
 constexpr int kPrepInFlight = 8;           // segments loaded at once per thread
 
-// One workgroup.  Pass 1 reads the table coalesced (segment s by thread
-// s mod blockDim, several segments in flight) and stores each segment's tile
-// count (it does not read the key schedules); pass 2 turns contiguous runs of counts into exclusive prefix sums
-// with a scan of the per-thread run totals.
+// One workgroup (a multiple of 64 threads).  Pass 1 reads the table
+// coalesced (segment s by thread s mod blockDim, several segments in flight)
+// and stores each segment's tile count (it does not read the key schedules);
+// pass 2 turns contiguous runs of counts into exclusive prefix sums with a
+// scan of the per-thread run totals: within each wave by lane shuffles, then
+// over the wave totals (one barrier instead of two per doubling step).
 __global__ __launch_bounds__(1024) void batched_prepare(const aes_segment_t *__restrict__ segs,
                                                         uint32_t nsegs, uint32_t nkeys, void *ws,
                                                         uint32_t tile_blocks)
 {
-    __shared__ uint32_t part[1024];
+    __shared__ uint32_t wave_total[16];
     __shared__ uint32_t cnt_lds[kPrepLdsSegs];
     __shared__ int bad_any;
     WsHeader *h = static_cast<WsHeader *>(ws);
@@ -131,16 +137,22 @@ __global__ __launch_bounds__(1024) void batched_prepare(const aes_segment_t *__r
 #pragma unroll 8
     for (uint32_t s = lo; s < hi; ++s)
         sum += cnt[s];
-    part[tid] = sum;
-    __syncthreads();
-    // inclusive scan of the per-thread sums (Hillis-Steele in LDS)
-    for (uint32_t off = 1; off < nt; off <<= 1) {
-        uint32_t v = tid >= off ? part[tid - off] : 0u;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
+    // inclusive scan of the per-thread sums: inside the wave, then the totals
+    // of the waves before this one
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    uint32_t incl = sum;
+#pragma unroll
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off, 64);
+        if (lane >= off)
+            incl += v;
     }
-    uint32_t run = part[tid] - sum;   // exclusive prefix of this run
+    if (lane == 63)
+        wave_total[wave] = incl;
+    __syncthreads();
+    for (uint32_t w = 0; w < wave; ++w)
+        incl += wave_total[w];
+    uint32_t run = incl - sum;   // exclusive prefix of this run
 #pragma unroll 8
     for (uint32_t s = lo; s < hi; ++s) {
         const uint32_t c = cnt[s];
@@ -151,8 +163,8 @@ __global__ __launch_bounds__(1024) void batched_prepare(const aes_segment_t *__r
     if (tid < kClaimParts)
         *claim_counter(ws, tid) = 0;
     if (tid == nt - 1) {
-        start[nsegs] = part[nt - 1];
-        h->ntiles = part[nt - 1];
+        start[nsegs] = incl;
+        h->ntiles = incl;
         h->tile_blocks = tile_blocks;
         h->status = bad_any ? (int32_t)AES_ERR_SEGMENT : (int32_t)AES_OK;
     }

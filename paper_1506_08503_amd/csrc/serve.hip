@@ -30,8 +30,7 @@ class HipServeDevice {
 public:
     HipServeDevice(const aes_serve_params_t &pr, const uint8_t *keys32, const uint8_t *key_len,
                    const uint8_t *pool, uint8_t *out)
-        : pr_(pr), keys32_(keys32), key_len_(key_len), pool_(pool), out_(out),
-          t0_(std::chrono::steady_clock::now())
+        : pr_(pr), keys32_(keys32), key_len_(key_len), pool_(pool), out_(out)
     {
         // waves of the batched kernel's grid (one 1,024-thread workgroup per CU)
         waves_ = 16u * (uint32_t)(device_cu_count() > 0 ? device_cu_count() : 256);
@@ -76,9 +75,10 @@ public:
                 hipMalloc((void **)&s.stage_d, stage_max) != hipSuccess)
                 return false;
         }
-        t0_ = std::chrono::steady_clock::now();
         return true;
     }
+
+    void start() { t0_ = std::chrono::steady_clock::now(); }
 
     double now() const
     {

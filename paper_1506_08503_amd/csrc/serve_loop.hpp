@@ -133,7 +133,8 @@ struct ServeBatchPlan {
 };
 
 // The loop.  Dev provides
-//   double now()                         seconds since the start of the run
+//   void start()                         start of the run: now() counts from here
+//   double now()                         seconds since start()
 //   int poll(uint32_t slot)              1 = the slot's batch has completed,
 //                                        0 = not yet, < 0 = device error
 //   aes_segment_t *segments(uint32_t slot, uint64_t k)   host room for the
@@ -185,6 +186,9 @@ aes_status_t serve_loop(const aes_serve_request_t *reqs, size_t nreq, size_t nke
     aes_serve_stats_t st{};
     uint64_t qh = 0, held = 0, arrived = pr.realtime ? 0 : nreq;
     const double window = pr.window_s;
+    // the clock starts once the loop's own set-up is done: arrival times
+    // count from here
+    dev.start();
     while (qh < nreq || !order.empty()) {
         const double now = dev.now();
         bool progressed = false;

@@ -31,6 +31,7 @@ struct SimDevice {
     std::vector<double> done_at;
     std::vector<std::vector<aes_segment_t>> segs;
 
+    void start() {}
     double now() const { return t; }
     int poll(uint32_t si) const { return t >= done_at[si] ? 1 : 0; }
     aes_segment_t *segments(uint32_t si, uint64_t k)

@@ -293,3 +293,25 @@ def test_serve_run_validation():
     # request whose output is larger than the whole area is rejected in the run)
     assert call(ob=15) == -9
 
+
+def test_bench_trace_summary(tmp_path):
+    """bench.py --trace-summary: per kernel, the last N dispatches of the
+    rocprofv3 kernel trace (the timed steps of a bench run come last)."""
+    import json
+    import subprocess
+    import sys
+    d = tmp_path / "prof" / "host"
+    d.mkdir(parents=True)
+    rows = ["Kind,Kernel_Name,Start_Timestamp,End_Timestamp"]
+    for i, ns in enumerate([9_000_000, 5_000_000, 2_000_000, 2_500_000, 3_000_000]):
+        rows.append("KERNEL_DISPATCH,ctr_grouped_kernel,%d,%d" % (10**9 * (i + 1), 10**9 * (i + 1) + ns))
+    rows.append("KERNEL_DISPATCH,other,5,10")
+    (d / "run_kernel_trace.csv").write_text("\n".join(rows) + "\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--trace-summary",
+                          str(tmp_path / "prof"), "--last", "3"], capture_output=True, text=True,
+                         check=True).stdout
+    s = json.loads(out)
+    assert s["ctr_grouped_kernel"] == {"calls": 5, "last": 3, "avg_ms": 2.5, "min_ms": 2.0,
+                                       "max_ms": 3.0}
+    assert s["other"]["calls"] == 1
