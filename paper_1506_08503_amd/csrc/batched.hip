@@ -170,26 +170,66 @@ __global__ __launch_bounds__(1024) void batched_prepare(const aes_segment_t *__r
     }
 }
 
-// Segment holding tile t: the last s with tile_start[s] <= t (empty segments
-// share their start with the next one).  Each round splits the candidate
-// range into 64 pieces, one per lane, and keeps the last piece whose first
-// entry is <= t.
-__device__ __forceinline__ uint32_t find_segment(const uint32_t *__restrict__ start,
-                                                 uint32_t nsegs, uint32_t t, uint32_t lane)
+// Segment holding tile t: the last s in [lo, hi) with start(s) <= t (empty
+// segments share their start with the next one), given start(lo) <= t.  Each
+// round splits the candidate range into 64 pieces, one per lane, and keeps
+// the last piece whose first entry is <= t.
+template <class Start>
+__device__ __forceinline__ uint32_t ballot_search(const Start &start, uint32_t lo, uint32_t hi,
+                                                  uint32_t t, uint32_t lane)
 {
-    uint32_t lo = 0, hi = nsegs;
     while (hi - lo > 1) {
         const uint32_t step = (hi - lo + 63u) / 64u;
         const uint32_t idx = lo + lane * step;
-        const bool ok = idx < hi && start[idx] <= t;
+        const bool ok = idx < hi && start(idx) <= t;
         const uint64_t m = __ballot(ok);
-        // lane 0 tests start[lo] <= t, which always holds: m is never 0 on a
+        // lane 0 tests start(lo) <= t, which always holds: m is never 0 on a
         // full wave (the guard keeps lo in range regardless)
         const uint32_t last = m ? 63u - (uint32_t)__clzll((long long)m) : 0u;
         lo += last * step;
         hi = min(lo + step, hi);
     }
     return lo;
+}
+
+__device__ __forceinline__ uint32_t find_segment(const uint32_t *__restrict__ start,
+                                                 uint32_t nsegs, uint32_t t, uint32_t lane)
+{
+    return ballot_search([start](uint32_t i) { return start[i]; }, 0, nsegs, t, lane);
+}
+
+// The table kernel keeps samples of tile_start in the LDS left beside its
+// tables: sample j = tile_start[j * stride], stride = ceil(nsegs / 7936), so
+// the search runs in LDS and then, when stride > 1, in one round of global
+// loads within the sampled range (10,000 segments: stride 2).  Without the
+// samples every tile took three rounds of dependent global loads.
+constexpr uint32_t kTileSamples = 7936;   // 31 KiB next to the 128 KiB of tables
+
+struct TileSamples {
+    uint32_t stride, count;
+};
+
+__device__ TileSamples load_tile_samples(uint32_t *smp, const uint32_t *__restrict__ start,
+                                         uint32_t nsegs)
+{
+    TileSamples ts;
+    ts.stride = nsegs ? (nsegs + kTileSamples - 1) / kTileSamples : 1u;
+    ts.count = (nsegs + ts.stride - 1) / ts.stride;
+    for (uint32_t j = threadIdx.x; j < ts.count; j += blockDim.x)
+        smp[j] = start[j * ts.stride];
+    return ts;
+}
+
+__device__ __forceinline__ uint32_t find_segment_sampled(const uint32_t *smp,
+                                                         const TileSamples &ts,
+                                                         const uint32_t *__restrict__ start,
+                                                         uint32_t nsegs, uint32_t t,
+                                                         uint32_t lane)
+{
+    const uint32_t j = ballot_search([smp](uint32_t i) { return smp[i]; }, 0, ts.count, t, lane);
+    const uint32_t lo = j * ts.stride;
+    return ballot_search([start](uint32_t i) { return start[i]; }, lo,
+                         min(lo + ts.stride, nsegs), t, lane);
 }
 
 // The next tile of a wave after its first (tile g of wave g), or ntiles when
@@ -344,17 +384,19 @@ __global__ __launch_bounds__(1024) void batched_ttable_kernel(
     uint8_t *out_base, void *ws)
 {
     __shared__ __attribute__((aligned(16))) char lds[kEncLdsBytes];
+    __shared__ uint32_t smp[kTileSamples];
+    WsHeader *h = static_cast<WsHeader *>(ws);
+    const uint32_t *start = tile_start_of(ws);
     fill_tables(lds, false);
+    const TileSamples ts = load_tile_samples(smp, start, nsegs);
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     const Lc lc = make_lc(lane);
-    WsHeader *h = static_cast<WsHeader *>(ws);
-    const uint32_t *start = tile_start_of(ws);
     const uint32_t ntiles = h->ntiles, tile_blocks = h->tile_blocks;
     const uint32_t nw = grid_waves();
     uint32_t part = first_part();
     for (uint32_t t = grid_wave(); t < ntiles; t = claim_tile(ws, part, nw, ntiles, lane)) {
-        const uint32_t s = find_segment(start, nsegs, t, lane);
+        const uint32_t s = find_segment_sampled(smp, ts, start, nsegs, t, lane);
         const TileJob j = make_job(segs, start, s, t, tile_blocks, ks_table, in_base, out_base);
         switch (j.ks->nr) {
         case 10: ttable_tile<10, BPL>(j, lds, lc, lane); break;
