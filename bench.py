@@ -87,6 +87,9 @@ def parse():
                         "--output-format csv wrote under DIR over the last --last dispatches "
                         "of each kernel")
     p.add_argument("--last", type=int, default=20)
+    p.add_argument("--split-gap-ms", type=float, default=0.0,
+                   help="with --trace-summary: also split the trace into runs at idle gaps "
+                        "longer than this (every kernel idle) and summarize each run")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     return p.parse_args()
 
@@ -353,26 +356,47 @@ def binding_roofline(lds_reads, nblocks, ms, pr):
     return res
 
 
-def trace_summary(root, last):
+def trace_summary(root, last, split_gap_ms=0.0):
     """Per kernel: calls in the trace, and count / average / min / max
     duration (ms) of its last `last` dispatches, from rocprofv3's kernel
-    trace CSV files under root."""
+    trace CSV files under root.  With split_gap_ms > 0, also per run: the
+    dispatches split where the GPU ran no kernel for longer than that."""
     import csv
     import glob
-    rows = {}
+    rows, allk = {}, []
     for path in sorted(glob.glob(os.path.join(root, "**", "*kernel_trace.csv"), recursive=True)):
         with open(path, newline="") as f:
             for r in csv.DictReader(f):
                 name = r["Kernel_Name"]
-                rows.setdefault(name, []).append(
-                    (int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+                ev = (int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+                rows.setdefault(name, []).append(ev)
+                allk.append(ev + (name,))
+
+    def stats(ts):
+        d = [(e - b) / 1e6 for b, e in ts]
+        return {"calls": len(d), "avg_ms": round(sum(d) / len(d), 4),
+                "min_ms": round(min(d), 4), "max_ms": round(max(d), 4)}
     out = {}
     for name, ts in rows.items():
         ts.sort()
-        tail = [(e - b) / 1e6 for b, e in ts[-last:]]
-        out[name] = {"calls": len(ts), "last": len(tail),
-                     "avg_ms": round(sum(tail) / len(tail), 4), "min_ms": round(min(tail), 4),
-                     "max_ms": round(max(tail), 4)}
+        out[name] = dict(stats(ts[-last:]), calls=len(ts), last=len(ts[-last:]))
+    if split_gap_ms > 0 and allk:
+        allk.sort()
+        runs, cur, busy_until = [], [], None
+        for b, e, name in allk:
+            if cur and b - busy_until > split_gap_ms * 1e6:
+                runs.append(cur)
+                cur = []
+            cur.append((b, e, name))
+            busy_until = e if busy_until is None or not cur[:-1] else max(busy_until, e)
+        runs.append(cur)
+        out["runs"] = []
+        for run in runs:
+            per = {}
+            for b, e, name in run:
+                per.setdefault(name, []).append((b, e))
+            out["runs"].append({"span_ms": round((max(e for _, e, _ in run) - run[0][0]) / 1e6, 3),
+                                "kernels": {n: stats(ts) for n, ts in per.items()}})
     return out
 
 
@@ -485,7 +509,8 @@ def main():
               "and this build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.trace_summary:
-        print(json.dumps(trace_summary(args.trace_summary, args.last)), flush=True)
+        print(json.dumps(trace_summary(args.trace_summary, args.last, args.split_gap_ms)),
+              flush=True)
         return
     if args.pmc_summary:
         print(json.dumps(pmc_summary(args.pmc_summary, args.last)), flush=True)

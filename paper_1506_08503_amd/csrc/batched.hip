@@ -199,11 +199,15 @@ __device__ __forceinline__ uint32_t find_segment(const uint32_t *__restrict__ st
 }
 
 // The table kernel keeps samples of tile_start in the LDS left beside its
-// tables: sample j = tile_start[j * stride], stride = ceil(nsegs / 7936), so
+// tables: sample j = tile_start[j * stride], stride = ceil(nsegs / 7168), so
 // the search runs in LDS and then, when stride > 1, in one round of global
 // loads within the sampled range (10,000 segments: stride 2).  Without the
-// samples every tile took three rounds of dependent global loads.
-constexpr uint32_t kTileSamples = 7936;   // 31 KiB next to the 128 KiB of tables
+// samples every tile took three rounds of dependent global loads.  28 KiB
+// leave 4 KiB of the CU's 160 KiB free: with 31 KiB (1 KiB free) the serving
+// loop's staging kernel (256 bytes of LDS) could no longer run on a CU beside
+// the other stream's table kernel, and its average time in the 1,024-row
+// closed loop went from 8 to 33 us.
+constexpr uint32_t kTileSamples = 7168;
 
 struct TileSamples {
     uint32_t stride, count;

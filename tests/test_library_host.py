@@ -315,3 +315,11 @@ def test_bench_trace_summary(tmp_path):
     assert s["ctr_grouped_kernel"] == {"calls": 5, "last": 3, "avg_ms": 2.5, "min_ms": 2.0,
                                        "max_ms": 3.0}
     assert s["other"]["calls"] == 1
+    # split into runs at idle gaps longer than 500 ms: the dispatches are 1 s
+    # apart and the first ("other", at 5 ns) is 1 s before the next
+    out = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--trace-summary",
+                          str(tmp_path / "prof"), "--last", "3", "--split-gap-ms", "500"],
+                         capture_output=True, text=True, check=True).stdout
+    runs = json.loads(out)["runs"]
+    assert len(runs) == 6 and runs[0]["kernels"]["other"]["calls"] == 1
+    assert runs[1]["kernels"]["ctr_grouped_kernel"]["avg_ms"] == 9.0
