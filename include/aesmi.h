@@ -14,8 +14,9 @@
  *  - Plain C types only.  Device buffers are raw device pointers; `stream` is
  *    a hipStream_t passed as void* (NULL = the null stream).
  *  - The caller owns every buffer.  No entry point allocates device memory,
- *    except that aes_batched_graph_create builds a HIP graph (set-up code)
- *    and aes_serve_run sets up its key cache and staging for a whole run;
+ *    except that aes_batched_graph_create builds a HIP graph (set-up code),
+ *    aes_serve_run sets up its key cache and staging for a whole run, and
+ *    aes_server_create does the same once for many runs;
  *    aes_ctr_xcrypt_batched_noalloc works in a static workspace of the
  *    library's own instead of a caller's.
  *  - Launching entry points are stream-ordered and asynchronous: AES_OK means
@@ -443,6 +444,33 @@ aes_status_t aes_serve_run(const aes_serve_request_t *reqs, size_t nreq, const u
                            size_t pool_bytes, void *out_dev, size_t out_bytes,
                            const aes_serve_params_t *params, double *latency_s,
                            uint64_t *out_off, aes_serve_stats_t *stats);
+
+/*
+ * A server: the same loop with its set-up done once.  aes_server_create
+ * allocates what aes_serve_run allocates per call (the device key table,
+ * per-stream pinned and device staging, streams and events) on the current
+ * device and copies the key set and parameters; aes_server_run plays a trace
+ * on it exactly as aes_serve_run does, but allocates nothing, and the key
+ * cache carries over from one run to the next (the rows stay expanded on
+ * the device: a later run's requests for those keys hit); the stats count
+ * the run's own hits and misses.  Runs on one server must not overlap (it
+ * is not thread-safe).  aes_server_destroy waits for the streams and frees
+ * everything; NULL is a no-op.
+ *   aes_server_create  errors as aes_serve_run's for the keys and
+ *                      parameters, AES_ERR_HIP when a set-up call fails;
+ *                      *server_out is NULL unless AES_OK
+ *   aes_server_run     errors as aes_serve_run's for the trace, pool and
+ *                      output area (key ids checked against the server's
+ *                      key set), AES_ERR_NULL for a NULL server
+ */
+typedef struct aes_server aes_server_t;
+aes_status_t aes_server_create(const uint8_t *keys32, const uint8_t *key_len, size_t nkeys,
+                               const aes_serve_params_t *params, aes_server_t **server_out);
+aes_status_t aes_server_run(aes_server_t *server, const aes_serve_request_t *reqs, size_t nreq,
+                            const void *pool_dev, size_t pool_bytes, void *out_dev,
+                            size_t out_bytes, double *latency_s, uint64_t *out_off,
+                            aes_serve_stats_t *stats);
+aes_status_t aes_server_destroy(aes_server_t *server);
 
 /* Text for a status code (static storage). */
 const char *aes_status_string(aes_status_t status);

@@ -151,6 +151,11 @@ def lib():
             "aes_batched_graph_destroy": ([vp], st),
             "aes_serve_run": ([vp, sz, vp, vp, sz, vp, sz, vp, sz, ctypes.POINTER(ServeParams),
                                vp, vp, ctypes.POINTER(ServeStats)], st),
+            "aes_server_create": ([vp, vp, sz, ctypes.POINTER(ServeParams), ctypes.POINTER(vp)],
+                                  st),
+            "aes_server_run": ([vp, vp, sz, vp, sz, vp, sz, vp, vp, ctypes.POINTER(ServeStats)],
+                               st),
+            "aes_server_destroy": ([vp], st),
             "aes_status_string": ([st], ctypes.c_char_p),
             "aes_version": ([], ctypes.c_char_p),
             "aes_device_cu_count": ([], ctypes.c_int),

@@ -475,18 +475,10 @@ aes_status_t aes_batched_graph_destroy(aes_batched_graph_t *graph)
     return (e1 == hipSuccess && e2 == hipSuccess) ? AES_OK : AES_ERR_HIP;
 }
 
-aes_status_t aes_serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8_t *keys32,
-                           const uint8_t *key_len, size_t nkeys, const void *pool_dev,
-                           size_t pool_bytes, void *out_dev, size_t out_bytes,
-                           const aes_serve_params_t *params, double *latency_s,
-                           uint64_t *out_off, aes_serve_stats_t *stats)
+static aes_status_t check_serve_setup(const uint8_t *keys32, const uint8_t *key_len,
+                                      size_t nkeys, const aes_serve_params_t *params)
 {
-    if (stats)
-        *stats = aes_serve_stats_t{};
-    if (nreq == 0)
-        return AES_OK;
-    if (!reqs || !keys32 || !key_len || !pool_dev || !out_dev || !params || !latency_s ||
-        !out_off)
+    if (!keys32 || !key_len || !params)
         return AES_ERR_NULL;
     const aes_serve_params_t &pr = *params;
     if (pr.nslots == 0 || pr.nstreams == 0 || pr.nstreams > kServeMaxStreams ||
@@ -497,6 +489,15 @@ aes_status_t aes_serve_run(const aes_serve_request_t *reqs, size_t nreq, const u
     for (size_t i = 0; i < nkeys; ++i)
         if (key_len[i] != 16 && key_len[i] != 24 && key_len[i] != 32)
             return AES_ERR_KEYLEN;
+    return AES_OK;
+}
+
+static aes_status_t check_serve_trace(const aes_serve_request_t *reqs, size_t nreq, size_t nkeys,
+                                      const void *pool_dev, size_t pool_bytes, void *out_dev,
+                                      size_t out_bytes, double *latency_s, uint64_t *out_off)
+{
+    if (!reqs || !pool_dev || !out_dev || !latency_s || !out_off)
+        return AES_ERR_NULL;
     if (!aligned16(pool_dev) || !aligned16(out_dev))
         return AES_ERR_ALIGN;
     const uintptr_t p0 = reinterpret_cast<uintptr_t>(pool_dev),
@@ -516,8 +517,70 @@ aes_status_t aes_serve_run(const aes_serve_request_t *reqs, size_t nreq, const u
             !(r.arrival_s < 1e18) || (i && r.arrival_s < reqs[i - 1].arrival_s))
             return AES_ERR_SEGMENT;
     }
-    return serve_run(reqs, nreq, keys32, key_len, nkeys, static_cast<const uint8_t *>(pool_dev),
-                     static_cast<uint8_t *>(out_dev), out_bytes, pr, latency_s, out_off, stats);
+    return AES_OK;
+}
+
+aes_status_t aes_server_create(const uint8_t *keys32, const uint8_t *key_len, size_t nkeys,
+                               const aes_serve_params_t *params, aes_server_t **server_out)
+{
+    if (!server_out)
+        return AES_ERR_NULL;
+    *server_out = nullptr;
+    const aes_status_t st = check_serve_setup(keys32, key_len, nkeys, params);
+    if (st != AES_OK)
+        return st;
+    return server_create(*params, keys32, key_len, nkeys, server_out);
+}
+
+aes_status_t aes_server_run(aes_server_t *server, const aes_serve_request_t *reqs, size_t nreq,
+                            const void *pool_dev, size_t pool_bytes, void *out_dev,
+                            size_t out_bytes, double *latency_s, uint64_t *out_off,
+                            aes_serve_stats_t *stats)
+{
+    if (stats)
+        *stats = aes_serve_stats_t{};
+    if (!server)
+        return AES_ERR_NULL;
+    if (nreq == 0)
+        return AES_OK;
+    const aes_status_t st = check_serve_trace(reqs, nreq, server_nkeys(server), pool_dev,
+                                              pool_bytes, out_dev, out_bytes, latency_s, out_off);
+    if (st != AES_OK)
+        return st;
+    return server_run(server, reqs, nreq, static_cast<const uint8_t *>(pool_dev),
+                      static_cast<uint8_t *>(out_dev), out_bytes, latency_s, out_off, stats);
+}
+
+aes_status_t aes_server_destroy(aes_server_t *server)
+{
+    server_destroy(server);
+    return AES_OK;
+}
+
+aes_status_t aes_serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8_t *keys32,
+                           const uint8_t *key_len, size_t nkeys, const void *pool_dev,
+                           size_t pool_bytes, void *out_dev, size_t out_bytes,
+                           const aes_serve_params_t *params, double *latency_s,
+                           uint64_t *out_off, aes_serve_stats_t *stats)
+{
+    if (stats)
+        *stats = aes_serve_stats_t{};
+    if (nreq == 0)
+        return AES_OK;
+    aes_status_t st = check_serve_setup(keys32, key_len, nkeys, params);
+    if (st == AES_OK)
+        st = check_serve_trace(reqs, nreq, nkeys, pool_dev, pool_bytes, out_dev, out_bytes,
+                               latency_s, out_off);
+    if (st != AES_OK)
+        return st;
+    aes_server_t *srv = nullptr;
+    st = server_create(*params, keys32, key_len, nkeys, &srv);
+    if (st != AES_OK)
+        return st;
+    st = server_run(srv, reqs, nreq, static_cast<const uint8_t *>(pool_dev),
+                    static_cast<uint8_t *>(out_dev), out_bytes, latency_s, out_off, stats);
+    server_destroy(srv);
+    return st;
 }
 
 const char *aes_status_string(aes_status_t status)

@@ -60,13 +60,16 @@ hipError_t stage_and_expand(const void *src_host, void *dst_dev, size_t bytes,
                             const uint8_t *keys32, const uint8_t *lens, const uint32_t *slots,
                             uint32_t nfill, aes_key_schedule_t *table, hipStream_t stream);
 
-// --- serving loop (serve.hip); arguments checked by aes_serve_run ----------
+// --- serving loop (serve.hip); arguments checked in api.hip ----------------
 constexpr uint32_t kServeMaxStreams = 8;
 constexpr uint32_t kServeMaxBatch = 65536;
-aes_status_t serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8_t *keys32,
-                       const uint8_t *key_len, size_t nkeys, const uint8_t *pool, uint8_t *out,
-                       uint64_t out_bytes, const aes_serve_params_t &pr, double *latency_s,
-                       uint64_t *out_off, aes_serve_stats_t *stats);
+aes_status_t server_create(const aes_serve_params_t &pr, const uint8_t *keys32,
+                           const uint8_t *key_len, size_t nkeys, aes_server_t **out);
+aes_status_t server_run(aes_server_t *srv, const aes_serve_request_t *reqs, size_t nreq,
+                        const uint8_t *pool, uint8_t *out, uint64_t out_bytes, double *latency_s,
+                        uint64_t *out_off, aes_serve_stats_t *stats);
+void server_destroy(aes_server_t *srv);
+size_t server_nkeys(const aes_server_t *srv);
 
 // --- batched persistent kernel (batched.hip) -------------------------------
 size_t batched_workspace_bytes(uint32_t nsegs);

@@ -12,13 +12,13 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "internal.hpp"
 #include "serve_loop.hpp"
 
 namespace aesmi {
-namespace {
 
 // The loop's device.  Per stream slot: staging for one batch at a time, k
 // requests with f key fills, in pinned host memory:
@@ -28,12 +28,20 @@ namespace {
 // the device staging and expands the fills straight from host memory.
 class HipServeDevice {
 public:
-    HipServeDevice(const aes_serve_params_t &pr, const uint8_t *keys32, const uint8_t *key_len,
-                   const uint8_t *pool, uint8_t *out)
-        : pr_(pr), keys32_(keys32), key_len_(key_len), pool_(pool), out_(out)
+    HipServeDevice(const aes_serve_params_t &pr, const uint8_t *keys32, const uint8_t *key_len)
+        : pr_(pr), keys32_(keys32), key_len_(key_len)
     {
         // waves of the batched kernel's grid (one 1,024-thread workgroup per CU)
         waves_ = 16u * (uint32_t)(device_cu_count() > 0 ? device_cu_count() : 256);
+    }
+    HipServeDevice(const HipServeDevice &) = delete;
+    HipServeDevice &operator=(const HipServeDevice &) = delete;
+
+    // The input pool and output area of the next run.
+    void bind(const uint8_t *pool, uint8_t *out)
+    {
+        pool_ = pool;
+        out_ = out;
     }
 
     ~HipServeDevice()
@@ -54,7 +62,7 @@ public:
         (void)hipFree(table_);
     }
 
-    // Key table, streams, events and staging for the whole run.
+    // Key table, streams, events and staging for every run of this device.
     bool setup()
     {
         const uint32_t maxb = pr_.max_batch_reqs;
@@ -178,27 +186,66 @@ private:
         return 1024;
     }
 
-    const aes_serve_params_t &pr_;
+    const aes_serve_params_t pr_;
     const uint8_t *keys32_, *key_len_;
-    const uint8_t *pool_;
-    uint8_t *out_;
+    const uint8_t *pool_ = nullptr;
+    uint8_t *out_ = nullptr;
     std::chrono::steady_clock::time_point t0_;
     uint32_t waves_ = 0;
     aes_key_schedule_t *table_ = nullptr;
     std::vector<Slot> slots_;
 };
 
-}  // namespace
+}  // namespace aesmi
 
-aes_status_t serve_run(const aes_serve_request_t *reqs, size_t nreq, const uint8_t *keys32,
-                       const uint8_t *key_len, size_t nkeys, const uint8_t *pool, uint8_t *out,
-                       uint64_t out_bytes, const aes_serve_params_t &pr, double *latency_s,
-                       uint64_t *out_off, aes_serve_stats_t *stats)
+// A server: the device of the loop (key table, streams, staging) and the key
+// cache, set up once and used by every run.
+struct aes_server {
+    std::vector<uint8_t> keys32, key_len;
+    aes_serve_params_t params;
+    aesmi::ServeKeyCache cache;
+    aesmi::HipServeDevice dev;
+
+    aes_server(const aes_serve_params_t &pr, const uint8_t *k32, const uint8_t *klen, size_t nkeys)
+        : keys32(k32, k32 + 32 * nkeys), key_len(klen, klen + nkeys), params(pr),
+          cache(nkeys, pr.nslots), dev(pr, keys32.data(), key_len.data())
+    {
+    }
+};
+
+namespace aesmi {
+
+aes_status_t server_create(const aes_serve_params_t &pr, const uint8_t *keys32,
+                           const uint8_t *key_len, size_t nkeys, aes_server_t **out)
 {
-    HipServeDevice dev(pr, keys32, key_len, pool, out);
-    if (!dev.setup())
+    aes_server_t *srv = new (std::nothrow) aes_server_t(pr, keys32, key_len, nkeys);
+    if (!srv)
         return AES_ERR_HIP;
-    return serve_loop(reqs, nreq, nkeys, pr, out_bytes, dev, latency_s, out_off, stats);
+    if (!srv->dev.setup()) {
+        delete srv;
+        return AES_ERR_HIP;
+    }
+    *out = srv;
+    return AES_OK;
+}
+
+aes_status_t server_run(aes_server_t *srv, const aes_serve_request_t *reqs, size_t nreq,
+                        const uint8_t *pool, uint8_t *out, uint64_t out_bytes, double *latency_s,
+                        uint64_t *out_off, aes_serve_stats_t *stats)
+{
+    srv->dev.bind(pool, out);
+    return serve_loop(reqs, nreq, srv->params, out_bytes, srv->cache, srv->dev, latency_s,
+                      out_off, stats);
+}
+
+void server_destroy(aes_server_t *srv)
+{
+    delete srv;
+}
+
+size_t server_nkeys(const aes_server_t *srv)
+{
+    return srv->key_len.size();
 }
 
 }  // namespace aesmi

@@ -143,12 +143,15 @@ struct ServeBatchPlan {
 //   void deliver(uint64_t first, uint64_t count)   results of a completed batch
 //                                        are readable until this returns
 //   void idle()                          called when a pass changed nothing
-// Arguments were checked by aes_serve_run.
+// The key cache kc may come from an earlier run on the same device (its
+// rows are still expanded there; no row may be pinned); the hit and miss
+// counts in stats are this run's.  Arguments were checked by the caller.
 template <class Dev>
-aes_status_t serve_loop(const aes_serve_request_t *reqs, size_t nreq, size_t nkeys,
-                        const aes_serve_params_t &pr, uint64_t out_bytes, Dev &dev,
-                        double *latency_s, uint64_t *out_off, aes_serve_stats_t *stats)
+aes_status_t serve_loop(const aes_serve_request_t *reqs, size_t nreq,
+                        const aes_serve_params_t &pr, uint64_t out_bytes, ServeKeyCache &kc,
+                        Dev &dev, double *latency_s, uint64_t *out_off, aes_serve_stats_t *stats)
 {
+    const uint64_t hits0 = kc.hits, misses0 = kc.misses;
     const uint32_t nstreams = pr.nstreams, maxb = pr.max_batch_reqs;
     // Rows one batch may take from the unpinned ones: with the whole cache a
     // batch of a small cache pins every row and the next batch cannot start
@@ -175,7 +178,6 @@ aes_status_t serve_loop(const aes_serve_request_t *reqs, size_t nreq, size_t nke
     std::vector<InFlight> slot(nstreams);
     std::vector<bool> busy(nstreams, false);
     std::deque<uint32_t> order;          // busy slots in submission order
-    ServeKeyCache kc(nkeys, pr.nslots);
     OutRing ring(out_bytes);
     // row -> slot whose in-flight batch expanded it (-1: none)
     std::vector<int32_t> filled_by(pr.nslots, -1);
@@ -303,8 +305,8 @@ aes_status_t serve_loop(const aes_serve_request_t *reqs, size_t nreq, size_t nke
     for (size_t i = 0; i < nreq; ++i)
         if (std::isfinite(complete[i]))
             latency_s[i] = complete[i] - (pr.realtime ? reqs[i].arrival_s : 0.0);
-    st.key_hits = kc.hits;
-    st.key_misses = kc.misses;
+    st.key_hits = kc.hits - hits0;
+    st.key_misses = kc.misses - misses0;
     st.max_out_used = ring.peak;
     if (stats)
         *stats = st;

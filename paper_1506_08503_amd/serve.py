@@ -611,6 +611,105 @@ class NativeResults:
         return self.out[o:o + int(self.size[i])]
 
 
+def _request_table(reqs: Requests):
+    from . import aesmi
+    tab = np.zeros(len(reqs), dtype=aesmi.serve_request_dtype())
+    tab["arrival_s"] = reqs.arrival
+    tab["in_off"] = reqs.in_off
+    tab["nbytes"] = reqs.size
+    tab["key_id"] = reqs.key_id
+    tab["ctr0"] = reqs.ctr0
+    tab["nonce"] = reqs.nonce
+    return tab
+
+
+def _key_arrays(keys: list):
+    keys32 = np.zeros((len(keys), 32), np.uint8)
+    klen = np.zeros(len(keys), np.uint8)
+    for i, k in enumerate(keys):
+        keys32[i, :len(k)] = np.frombuffer(k, np.uint8)
+        klen[i] = len(k)
+    return keys32, klen
+
+
+def _stats_of(st, lat, n):
+    return Stats(completed=int(st.completed), rejected=int(st.rejected), bytes=int(st.bytes),
+                 batches=int(st.batches), elapsed_s=float(st.elapsed_s), latency_s=lat,
+                 admission_wait_s=np.zeros(n), key_hits=int(st.key_hits),
+                 key_misses=int(st.key_misses), max_inflight=int(st.max_inflight),
+                 max_held=int(st.max_held), max_out_used=int(st.max_out_used))
+
+
+class NativeServer:
+    """aes_server_create / _run / _destroy: the library's request loop set up
+    once (key table, streams, staging) for many runs on the current device;
+    the key cache carries over from run to run.  on_batch(first, count,
+    out_off) is called as each batch completes (see run_native)."""
+
+    def __init__(self, keys: list, nslots: int, nstreams: int = 2, hbm_budget: int = 4 << 30,
+                 max_batch_reqs: int = 8192, max_batch_bytes: int = 64 << 20,
+                 window_s: float = 25e-6, realtime: bool = True, on_batch=None):
+        from . import aesmi
+        self._am = aesmi
+        self.keys = keys
+        self._keys32, self._klen = _key_arrays(keys)
+        self._errors = []
+        self._off = None
+        self._cb = aesmi.SERVE_BATCH_FN()
+        if on_batch is not None:
+            def _cb(user, first, count):
+                try:
+                    on_batch(int(first), int(count), self._off)
+                except BaseException as e:     # an exception cannot cross the C frame
+                    self._errors.append(e)
+            self._cb = aesmi.SERVE_BATCH_FN(_cb)
+        self._prm = aesmi.ServeParams(nslots, nstreams, max_batch_reqs, 1 if realtime else 0,
+                                      hbm_budget, max_batch_bytes, window_s, self._cb, None)
+        h = ctypes.c_void_p()
+        aesmi._check(aesmi.lib().aes_server_create(
+            self._keys32.ctypes.data, self._klen.ctypes.data, len(keys), ctypes.byref(self._prm),
+            ctypes.byref(h)), "aes_server_create")
+        self._h = h
+
+    def run(self, pool, reqs: Requests, out=None):
+        """Play one trace; returns (Stats, NativeResults) as run_native."""
+        import torch
+        am = self._am
+        if not self._h:
+            raise RuntimeError("server is closed")
+        am._dev_u8(pool, "pool")
+        n = len(reqs)
+        tab = _request_table(reqs)
+        if out is None:
+            need = int(((reqs.size + 15) // 16 * 16).sum())
+            out = torch.empty(max(need, 16), dtype=torch.uint8, device=pool.device)
+        am._dev_u8(out, "output area")
+        lat = np.empty(n, np.float64)
+        self._off = off = np.empty(n, np.uint64)
+        self._errors.clear()
+        st = am.ServeStats()
+        with torch.cuda.device(pool.device):
+            torch.cuda.synchronize(pool.device)
+            am._check(am.lib().aes_server_run(
+                self._h, tab.ctypes.data, n, pool.data_ptr(), pool.numel(), out.data_ptr(),
+                out.numel(), lat.ctypes.data, off.ctypes.data, ctypes.byref(st)),
+                "aes_server_run")
+        if self._errors:
+            raise self._errors[0]
+        return _stats_of(st, lat, n), NativeResults(out, off, reqs.size)
+
+    def close(self):
+        if self._h:
+            self._am._check(self._am.lib().aes_server_destroy(self._h), "aes_server_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def run_native(pool, keys: list, reqs: Requests, nslots: int, nstreams: int = 2,
                hbm_budget: int = 4 << 30, max_batch_reqs: int = 8192,
                max_batch_bytes: int = 64 << 20, window_s: float = 25e-6,
@@ -628,18 +727,8 @@ def run_native(pool, keys: list, reqs: Requests, nslots: int, nstreams: int = 2,
     from . import aesmi
     aesmi._dev_u8(pool, "pool")
     n = len(reqs)
-    tab = np.zeros(n, dtype=aesmi.serve_request_dtype())
-    tab["arrival_s"] = reqs.arrival
-    tab["in_off"] = reqs.in_off
-    tab["nbytes"] = reqs.size
-    tab["key_id"] = reqs.key_id
-    tab["ctr0"] = reqs.ctr0
-    tab["nonce"] = reqs.nonce
-    keys32 = np.zeros((len(keys), 32), np.uint8)
-    klen = np.zeros(len(keys), np.uint8)
-    for i, k in enumerate(keys):
-        keys32[i, :len(k)] = np.frombuffer(k, np.uint8)
-        klen[i] = len(k)
+    tab = _request_table(reqs)
+    keys32, klen = _key_arrays(keys)
     need = int(((reqs.size + 15) // 16 * 16).sum())
     if out is None:
         out = torch.empty(max(need, 16), dtype=torch.uint8, device=pool.device)
@@ -666,9 +755,4 @@ def run_native(pool, keys: list, reqs: Requests, nslots: int, nstreams: int = 2,
             lat.ctypes.data, off.ctypes.data, ctypes.byref(st)), "aes_serve_run")
     if errors:
         raise errors[0]
-    stats = Stats(completed=int(st.completed), rejected=int(st.rejected), bytes=int(st.bytes),
-                  batches=int(st.batches), elapsed_s=float(st.elapsed_s), latency_s=lat,
-                  admission_wait_s=np.zeros(n), key_hits=int(st.key_hits),
-                  key_misses=int(st.key_misses), max_inflight=int(st.max_inflight),
-                  max_held=int(st.max_held), max_out_used=int(st.max_out_used))
-    return stats, NativeResults(out, off, reqs.size)
+    return _stats_of(st, lat, n), NativeResults(out, off, reqs.size)

@@ -95,7 +95,8 @@ int run_loop()
     std::vector<double> lat(nreq);
     std::vector<uint64_t> off(nreq);
     aes_serve_stats_t st{};
-    if (aesmi::serve_loop(reqs.data(), nreq, nkeys, pr, out_bytes, dev, lat.data(), off.data(),
+    aesmi::ServeKeyCache kc(nkeys, nslots);
+    if (aesmi::serve_loop(reqs.data(), nreq, pr, out_bytes, kc, dev, lat.data(), off.data(),
                           &st) != AES_OK)
         return 2;
     for (double v : lat)

@@ -230,3 +230,43 @@ def test_native_small_output_ring(oracle, realtime):
     with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as pool_ex:
         bad = [i for i, ok in zip(range(nreq), pool_ex.map(agrees, range(nreq))) if not ok]
     assert not bad, bad[:10]
+
+
+def test_native_server_object_runs_twice(oracle):
+    """aes_server_create once, two traces through aes_server_run: the key
+    cache carries over (the second run hits keys the first one loaded), no
+    result differs from the request run alone or from the oracle, and the
+    results are right in both runs."""
+    pool_bytes = 16 << 20
+    g = np.random.Generator(np.random.PCG64(71))
+    pool_h = np.frombuffer(g.bytes(pool_bytes), np.uint8).copy()
+    pool = torch.from_numpy(pool_h).to(DEV)
+    rs1 = wl.serving_inputs(1200, 3e5, nkeys=40, median=4096, sigma=1.5, max_size=256 << 10,
+                            seed=72)
+    keys = rs1.keys
+    reqs1 = serve.requests_from_stream(rs1, pool_bytes, seed=73)
+    rs2 = wl.serving_inputs(900, 3e5, nkeys=40, median=4096, sigma=1.5, max_size=256 << 10,
+                            seed=74)
+    reqs2 = serve.requests_from_stream(rs2, pool_bytes, seed=75)
+    srv = serve.NativeServer(keys, nslots=64, nstreams=2, max_batch_reqs=512)
+    try:
+        st1, res1 = srv.run(pool, reqs1)
+        st2, res2 = srv.run(pool, reqs2)
+    finally:
+        srv.close()
+    torch.cuda.synchronize()
+    assert st1.completed == len(reqs1) and st2.completed == len(reqs2)
+    # misses count requests whose key was filled for their batch: every key
+    # missed in the first run, none in the second
+    assert st1.key_misses >= 40 and st2.key_misses == 0 and st2.key_hits == len(reqs2)
+    for reqs, res, seed in ((reqs1, res1, 1), (reqs2, res2, 2)):
+        for i in range(len(reqs)):
+            a, n = int(reqs.in_off[i]), int(reqs.size[i])
+            ks = am.key_schedule(keys[reqs.key_id[i]], DEV)
+            alone = am.ctr_xcrypt(ks, reqs.nonce[i].tobytes(), int(reqs.ctr0[i]), pool[a:a + n])
+            assert torch.equal(res[i], alone), (seed, i)
+        for i in range(0, len(reqs), 60):
+            a, n = int(reqs.in_off[i]), int(reqs.size[i])
+            exp = oracle.ctr_xcrypt(keys[reqs.key_id[i]], reqs.nonce[i].tobytes(),
+                                    int(reqs.ctr0[i]), pool_h[a:a + n])
+            assert np.array_equal(res[i].cpu().numpy(), exp), (seed, i)

@@ -157,6 +157,32 @@ def test_batched_validation():
     assert L.aes_batched_graph_launch(None, None) == -1
 
 
+def test_server_validation():
+    """aes_server_create / _run / _destroy check keys, parameters and the
+    trace before any HIP call."""
+    keys32 = np.zeros((2, 32), np.uint8)
+    klen = np.array([16, 32], np.uint8)
+    prm = am.ServeParams(16, 2, 1024, 1, 1 << 30, 1 << 26, 50e-6)
+    h = VP(123)
+    assert L.aes_server_create(keys32.ctypes.data, klen.ctypes.data, 2, ctypes.byref(prm),
+                               None) == -1
+    assert L.aes_server_create(None, klen.ctypes.data, 2, ctypes.byref(prm),
+                               ctypes.byref(h)) == -1 and not h.value
+    bad = am.ServeParams(16, 0, 1024, 1, 1 << 30, 1 << 26, 50e-6)
+    assert L.aes_server_create(keys32.ctypes.data, klen.ctypes.data, 2, ctypes.byref(bad),
+                               ctypes.byref(h)) == -9
+    k2 = np.array([16, 17], np.uint8)
+    assert L.aes_server_create(keys32.ctypes.data, k2.ctypes.data, 2, ctypes.byref(prm),
+                               ctypes.byref(h)) == -2
+    st = am.ServeStats()
+    reqs = np.zeros(1, dtype=am.serve_request_dtype())
+    reqs["nbytes"] = 16
+    lat, off = np.zeros(1), np.zeros(1, np.uint64)
+    assert L.aes_server_run(None, reqs.ctypes.data, 1, VP(0x100000), 1 << 20, VP(0x400000),
+                            1 << 20, lat.ctypes.data, off.ctypes.data, ctypes.byref(st)) == -1
+    assert L.aes_server_destroy(None) == 0
+
+
 def test_batched_noalloc_validation():
     """The allocation-free batched call checks its arguments before any HIP
     call: more segments than its static workspace holds, a bad tune or a
