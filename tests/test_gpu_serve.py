@@ -234,9 +234,9 @@ def test_native_small_output_ring(oracle, realtime):
 
 def test_native_server_object_runs_twice(oracle):
     """aes_server_create once, two traces through aes_server_run: the key
-    cache carries over (the second run hits keys the first one loaded), no
-    result differs from the request run alone or from the oracle, and the
-    results are right in both runs."""
+    cache carries over (the second run hits keys the first one loaded), and
+    in both runs every result equals the request run alone and sampled ones
+    the oracle."""
     pool_bytes = 16 << 20
     g = np.random.Generator(np.random.PCG64(71))
     pool_h = np.frombuffer(g.bytes(pool_bytes), np.uint8).copy()

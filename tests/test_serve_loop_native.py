@@ -89,11 +89,11 @@ def trace(seed, n, nkeys, rate, median, sigma, max_size):
 
 
 def run_both(driver, arrival, size, key, nkeys, nslots, nstreams, maxb, budget, max_bytes,
-             window, out_bytes, latency=20e-6, rate=2e9, tick=1e-6):
+             window, out_bytes, latency=20e-6, rate=2e9, tick=1e-6, realtime=True):
     n = size.size
-    lines = ["loop %d %d %d %d %d 1 %d %d %.17g %d %.17g %.17g %.17g" % (
-        n, nkeys, nslots, nstreams, maxb, budget, max_bytes, window, out_bytes, latency, rate,
-        tick)]
+    lines = ["loop %d %d %d %d %d %d %d %d %.17g %d %.17g %.17g %.17g" % (
+        n, nkeys, nslots, nstreams, maxb, int(realtime), budget, max_bytes, window, out_bytes,
+        latency, rate, tick)]
     lines += ["%.17g %d %d" % (a, s, k) for a, s, k in zip(arrival, size, key)]
     res = subprocess.run([driver], input="\n".join(lines) + "\n", capture_output=True,
                          text=True, timeout=60)
@@ -111,7 +111,7 @@ def run_both(driver, arrival, size, key, nkeys, nslots, nstreams, maxb, budget, 
     srv = serve.Server(ex, serve.KeyCache(nslots, nkeys), budget, max_batch_bytes=max_bytes,
                        max_batch_reqs=maxb, window_s=window, clock=clock, out_bytes=out_bytes,
                        row_cap=max(1, nslots // nstreams))
-    st, _ = srv.run(reqs)
+    st, _ = srv.run(reqs, realtime=realtime)
     p_stats = [st.completed, st.rejected, st.batches, st.bytes, st.key_hits, st.key_misses,
                st.max_held, st.max_out_used, st.max_inflight]
     return (c_batches, c_lat, c_stats), (ex.log, st.latency_s, p_stats)
@@ -157,6 +157,18 @@ def test_loop_equals_python_model(driver, case):
             first, count, base = (int(v) for v in l.split()[1:4])
             assert base == pos, l[:80]
             pos += int(lin[first + count] - lin[first])
+
+
+def test_closed_loop_equals_python_model(driver):
+    """The whole trace present at the start (realtime off): a backlog cut by
+    the batch limits, the ring and a small key cache."""
+    arrival, size, key = trace(8, 1200, 60, 1e6, 4096, 1.5, 64 << 10)
+    arrival[:] = 0.0
+    (cb, cl, cs), (pb, pl, ps) = run_both(driver, arrival, size, key, 60, 12, 3, maxb=200,
+                                          budget=2 << 20, max_bytes=512 << 10, window=25e-6,
+                                          out_bytes=300 << 10, realtime=False)
+    assert cb == pb and np.array_equal(cl, pl) and cs == ps
+    assert cs[0] == size.size and cs[8] == 3 and len(cb) > 10
 
 
 def test_loop_with_no_limits_makes_progress(driver):
