@@ -240,28 +240,42 @@ __device__ __forceinline__ uint32_t find_segment_sampled(const uint32_t *smp,
 // none is left.  Counter p hands out tiles dyn0 + kClaimParts k + p, one per
 // atomic add; a wave starts at counter `part` and moves on to the next one
 // when it runs dry, so every tile is taken exactly once and waves that finish
-// early take work from the others.  Measured on the 10^4-message workload
+// early take work from the others.  A counter found dry is marked in the
+// workgroup's LDS mask `dry`, and the other waves of the workgroup skip it
+// without an add: at the end of a launch each workgroup, not each wave, pays
+// the dependent adds that find the 16 counters empty (an add is a round trip
+// to memory shared by all XCDs).  Measured on the 10^4-message workload
 // (1,024-thread workgroups): one counter, 2,048-block tiles 0.480 ms and
 // 256-block tiles 2.20 ms (claim bound); static first tiles and 16 counters
-// 0.452 and 0.72 ms.  A plain load of the counter before each add (to skip
-// adds on counters already past the end) made every tile size slower, and
-// claiming chunks of consecutive tiles per add was slower at 2048-4096
-// blocks per tile (waves then stream through separate regions).
-__device__ __forceinline__ uint32_t claim_tile(void *ws, uint32_t &part, uint32_t dyn0,
-                                               uint32_t ntiles, uint32_t lane)
+// 0.452 and 0.72 ms.  The mask: 64 MiB of lognormal request sizes (2,299
+// messages, 5,730 tiles of 1,024 blocks) 92.7 -> 68.8 us, 16,384 messages of
+// 4 KiB 125 -> 89 us, 10^4 messages 0.429 ms at 1,024 blocks.  A plain load of the counter before each add (to skip
+// adds on exhausted counters) made every tile size slower, and claiming
+// chunks of consecutive tiles per add was slower at 2048-4096 blocks per tile
+// (waves then stream through separate regions).
+__device__ __forceinline__ uint32_t claim_tile(void *ws, uint32_t *dry, uint32_t &part,
+                                               uint32_t dyn0, uint32_t ntiles, uint32_t lane)
 {
     for (uint32_t tried = 0; tried < kClaimParts; ++tried) {
         uint32_t t = ntiles;
         // a counter whose first tile is past the end is never touched
-        if (lane == 0 && (uint64_t)dyn0 + part < ntiles) {
-            const uint64_t t2 =
-                (uint64_t)dyn0 + (uint64_t)atomicAdd(claim_counter(ws, part), 1u) * kClaimParts + part;
-            if (t2 < ntiles)
-                t = (uint32_t)t2;
+        const uint32_t dm = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(dry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+        const bool skip = (uint64_t)dyn0 + part >= ntiles || ((dm >> part) & 1u);
+        if (!skip) {
+            if (lane == 0) {
+                const uint64_t t2 = (uint64_t)dyn0 +
+                                    (uint64_t)atomicAdd(claim_counter(ws, part), 1u) * kClaimParts +
+                                    part;
+                if (t2 < ntiles)
+                    t = (uint32_t)t2;
+                else
+                    atomicOr(dry, 1u << part);
+            }
+            t = __builtin_amdgcn_readfirstlane(t);
+            if (t < ntiles)
+                return t;
         }
-        t = __builtin_amdgcn_readfirstlane(t);
-        if (t < ntiles)
-            return t;
         part = part + 1 == kClaimParts ? 0u : part + 1;
     }
     return ntiles;
@@ -328,11 +342,66 @@ __device__ __forceinline__ TileJob make_job(const aes_segment_t *__restrict__ se
     return j;
 }
 
+// The last blocks [b, b + 64 NB) of a tile, NB per lane in one pass: block i
+// (lane (i - b) mod 64, slot (i - b) / 64) is loaded and stored whole when
+// i < j.nfull; the message's partial last block, when this tile holds it, is
+// enciphered in the same pass and its bytes go out from lanes 0..tail-1; the
+// other slots are enciphered and dropped.  One pass with NB independent
+// blocks per lane instead of NB dependent passes of one, plus one more for a
+// partial block (about 5% on 64 MiB of lognormal request sizes, relative to
+// the same bytes in 1 MiB messages).
+template <int NR, int NB>
+__device__ __forceinline__ void ttable_rest(const TileJob &j, uint64_t b, const uint32_t (&pre)[4],
+                                            const char *lds, const Lc &lc, uint32_t lane)
+{
+    const uint32_t *rk = j.ks->rk_enc;
+    uint32_t s[NB][4];
+    u32x4 x[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const uint64_t i = b + lane + 64u * q;
+        x[q] = i < j.nfull ? __builtin_nontemporal_load(j.in + i) : u32x4{0, 0, 0, 0};
+        const uint32_t w3 = bswap32(j.ctr0 + (uint32_t)i) ^ rk[3];
+        s[q][0] = pre[0] ^ TL(3, w3, 3);
+        s[q][1] = pre[1] ^ TL(2, w3, 2);
+        s[q][2] = pre[2] ^ TL(1, w3, 1);
+        s[q][3] = pre[3] ^ TL(0, w3, 0);
+    }
+    enc_rounds<NR, 2, NB>(s, rk, lds, lc);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const uint64_t i = b + lane + 64u * q;
+        if (i < j.nfull)
+            __builtin_nontemporal_store(u32x4{x[q].x ^ s[q][0], x[q].y ^ s[q][1],
+                                              x[q].z ^ s[q][2], x[q].w ^ s[q][3]},
+                                        j.out + i);
+    }
+    if (j.tail && j.nfull >= b && j.nfull < b + 64u * NB && j.b1 == j.nfull + 1) {
+        const uint32_t d = (uint32_t)(j.nfull - b), src_lane = d & 63u, slot = d >> 6;
+        uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            if (slot == (uint32_t)q) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    w[c] = (uint32_t)__builtin_amdgcn_readlane((int)s[q][c], (int)src_lane);
+            }
+        const uint32_t k = lane & 15u;
+        const uint32_t wk = k < 8u ? (k < 4u ? w[0] : w[1]) : (k < 12u ? w[2] : w[3]);
+        if (lane < j.tail) {
+            const uint8_t *src = reinterpret_cast<const uint8_t *>(j.in + j.nfull);
+            uint8_t *dst = reinterpret_cast<uint8_t *>(j.out + j.nfull);
+            dst[k] = src[k] ^ (uint8_t)(wk >> (8u * (k & 3u)));
+        }
+    }
+}
+
 // Blocks [b0, b1) of one message on one wave with the table kernel.  With
 // four blocks per lane: whole 256-counter groups with the round-1/2
 // precomputation when the counters are group aligned, four blocks per lane
 // otherwise; with two or one: that many blocks per lane and the round-1
-// terms of the nonce columns only.  Then the rest one block per lane.
+// terms of the nonce columns only.  Then the rest, with the partial last
+// block, in passes of up to BPL blocks per lane.
 template <int NR, int BPL>
 __device__ void ttable_tile(const TileJob &j, const char *lds, const Lc &lc, uint32_t lane)
 {
@@ -363,20 +432,21 @@ __device__ void ttable_tile(const TileJob &j, const char *lds, const Lc &lc, uin
             ctr_blocks<NR, BPL>(rk, j.in, j.out, b + lane, 64, j.ctr0, pre[0], pre[1], pre[2],
                                 pre[3], lds, lc);
     }
-    for (uint64_t i = b + lane; i < hi; i += 64)
-        ctr_blocks<NR, 1>(rk, j.in, j.out, i, 0, j.ctr0, pre[0], pre[1], pre[2], pre[3], lds, lc);
-    if (j.tail && j.b1 == j.nfull + 1) {
-        // The partial last block: lane k < tail computes the keystream block
-        // and handles byte k, so the bytes go out in one load and one store
-        // instead of a loop of dependent byte accesses on one lane.
-        uint32_t s1[1][4] = {{u0, u1, u2, bswap32(j.ctr0 + (uint32_t)j.nfull) ^ rk[3]}};
-        enc_rounds<NR, 1, 1>(s1, rk, lds, lc);
-        const uint32_t k = lane & 15u;
-        const uint32_t w = k < 8u ? (k < 4u ? s1[0][0] : s1[0][1]) : (k < 12u ? s1[0][2] : s1[0][3]);
-        if (lane < j.tail) {
-            const uint8_t *src = reinterpret_cast<const uint8_t *>(j.in + j.nfull);
-            uint8_t *dst = reinterpret_cast<uint8_t *>(j.out + j.nfull);
-            dst[k] = src[k] ^ (uint8_t)(w >> (8u * (k & 3u)));
+    // the rest of the tile, the partial last block included (b1 counts it)
+    while (b < j.b1) {
+        const uint64_t r = j.b1 - b;
+        if (BPL >= 4 && r > 192u) {
+            ttable_rest<NR, (BPL >= 4 ? 4 : 1)>(j, b, pre, lds, lc, lane);
+            b += 256u;
+        } else if (BPL >= 4 && r > 128u) {
+            ttable_rest<NR, (BPL >= 4 ? 3 : 1)>(j, b, pre, lds, lc, lane);
+            b += 192u;
+        } else if (BPL >= 2 && r > 64u) {
+            ttable_rest<NR, (BPL >= 2 ? 2 : 1)>(j, b, pre, lds, lc, lane);
+            b += 128u;
+        } else {
+            ttable_rest<NR, 1>(j, b, pre, lds, lc, lane);
+            b += 64u;
         }
     }
 }
@@ -389,8 +459,11 @@ __global__ __launch_bounds__(1024) void batched_ttable_kernel(
 {
     __shared__ __attribute__((aligned(16))) char lds[kEncLdsBytes];
     __shared__ uint32_t smp[kTileSamples];
+    __shared__ uint32_t dry;
     WsHeader *h = static_cast<WsHeader *>(ws);
     const uint32_t *start = tile_start_of(ws);
+    if (threadIdx.x == 0)
+        dry = 0;
     fill_tables(lds, false);
     const TileSamples ts = load_tile_samples(smp, start, nsegs);
     __syncthreads();
@@ -399,7 +472,7 @@ __global__ __launch_bounds__(1024) void batched_ttable_kernel(
     const uint32_t ntiles = h->ntiles, tile_blocks = h->tile_blocks;
     const uint32_t nw = grid_waves();
     uint32_t part = first_part();
-    for (uint32_t t = grid_wave(); t < ntiles; t = claim_tile(ws, part, nw, ntiles, lane)) {
+    for (uint32_t t = grid_wave(); t < ntiles; t = claim_tile(ws, &dry, part, nw, ntiles, lane)) {
         const uint32_t s = find_segment_sampled(smp, ts, start, nsegs, t, lane);
         const TileJob j = make_job(segs, start, s, t, tile_blocks, ks_table, in_base, out_base);
         switch (j.ks->nr) {
@@ -425,13 +498,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const aes_key_schedule_t *__restrict__ ks_table, const uint8_t *in_base,
     uint8_t *out_base, void *ws)
 {
+    __shared__ uint32_t dry;
     const uint32_t lane = threadIdx.x & 63u;
     WsHeader *h = static_cast<WsHeader *>(ws);
     const uint32_t *start = tile_start_of(ws);
+    if (threadIdx.x == 0)
+        dry = 0;
+    __syncthreads();
     const uint32_t ntiles = h->ntiles, tile_blocks = h->tile_blocks;
     const uint32_t nw = grid_waves();
     uint32_t part = first_part();
-    for (uint32_t t = grid_wave(); t < ntiles; t = claim_tile(ws, part, nw, ntiles, lane)) {
+    for (uint32_t t = grid_wave(); t < ntiles; t = claim_tile(ws, &dry, part, nw, ntiles, lane)) {
         const uint32_t s = find_segment(start, nsegs, t, lane);
         const TileJob j = make_job(segs, start, s, t, tile_blocks, ks_table, in_base, out_base);
         switch (j.ks->nr) {
@@ -490,7 +567,8 @@ hipError_t batched_ctr(const aes_segment_t *segs, uint32_t nsegs,
     const bool bs = layout == AES_LAYOUT_BITSLICE;
     uint32_t wg = tune && tune->wg_size ? tune->wg_size : (bs ? 256u : 1024u);
     uint32_t per_cu = tune && tune->grid_per_cu ? tune->grid_per_cu : (bs ? 2u : 1u);
-    uint32_t tile = tune && tune->tile_blocks ? tune->tile_blocks : kBatchedTileBlocks;
+    uint32_t tile = tune && tune->tile_blocks ? tune->tile_blocks
+                                              : (bs ? kBatchedBitsliceTileBlocks : kBatchedTileBlocks);
     const uint32_t bpl = tune && tune->blocks_per_lane ? tune->blocks_per_lane : 4u;
     if (bpl != 1 && bpl != 2 && bpl != 4)
         return hipErrorInvalidConfiguration;

@@ -169,21 +169,20 @@ private:
 
     // Tile of the batched kernel for a serving batch of `blocks` blocks.  A
     // wave works through a tile alone, so a batch with fewer tiles than the
-    // grid has waves takes as long as one wave's tile: small batches get
-    // small tiles.  Large ones keep 1,024 blocks, where fewer tiles cost less
-    // per-tile set-up.  Measured (1,024 key rows, lognormal mix, median
-    // 4 KiB): 1,024-block tiles 26.3-27.0 M requests/s closed loop and p50/p99
-    // 0.088/0.116 ms at 8 M requests/s offered (batches of ~400, ~12 MB);
-    // 256-block tiles 22.4 M/s but p50 0.065 ms at 8 M/s, and p99 0.22 ms at
-    // 14 M/s; 100 messages of 32 KiB take 33.8 us with 1,024-block tiles and
-    // 20.1 us with 256.
+    // grid has waves takes as long as one wave's tile, and tiles claimed late
+    // set the end of the launch: serving batches (up to 64 MiB by default,
+    // i.e. up to about 1,024 blocks per wave) get 256-block tiles; batches
+    // several times larger, where fewer tiles cost less per-tile set-up,
+    // 1,024.  Measured, one 64 MiB batch of the lognormal request mix (2,160
+    // requests, half AES-256): 256 / 512 / 1,024 / 2,048-block tiles 71.8 /
+    // 79.1 / 80.7 / 115.5 us; in the 1,024-row closed loop 256, 512 and the
+    // earlier rule (1,024 above 256 blocks per wave) all gave 33.7-34.1 M
+    // requests/s, with p50/p99 at 80% load 0.088/0.157 ms for 256 against
+    // 0.118/0.174 ms; 100 messages of 32 KiB take 20.1 us with 256-block
+    // tiles and 33.8 us with 1,024.
     static uint32_t serve_tile(uint64_t blocks, uint32_t waves)
     {
-        if (blocks <= 128ull * waves)
-            return 256;
-        if (blocks <= 256ull * waves)
-            return 512;
-        return 1024;
+        return blocks <= 2048ull * waves ? 256u : 1024u;
     }
 
     const aes_serve_params_t pr_;

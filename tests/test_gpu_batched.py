@@ -30,7 +30,10 @@ TUNES = [None,
          {"layout": am.LAYOUT_TTABLE, "tile_blocks": 512, "wg_size": 256, "grid_per_cu": 4,
           "blocks_per_lane": 1},
          {"layout": am.LAYOUT_BITSLICE, "tile_blocks": 2048, "wg_size": 256, "grid_per_cu": 2},
-         {"layout": am.LAYOUT_BITSLICE, "tile_blocks": 4096, "wg_size": 64, "grid_per_cu": 4}]
+         {"layout": am.LAYOUT_BITSLICE, "tile_blocks": 4096, "wg_size": 64, "grid_per_cu": 4},
+         # library default tile and shape of each layout
+         {"layout": am.LAYOUT_TTABLE},
+         {"layout": am.LAYOUT_BITSLICE}]
 
 
 def _rng(seed):
@@ -105,8 +108,9 @@ def run_case(case, tune, in_place=False):
 def _tune_id(t):
     if t is None:
         return "default"
-    return "%s-t%d-w%d-g%d-b%d" % ("bs" if t["layout"] == 2 else "tt", t["tile_blocks"],
-                                  t["wg_size"], t["grid_per_cu"], t.get("blocks_per_lane", 0))
+    return "%s-t%d-w%d-g%d-b%d" % ("bs" if t["layout"] == 2 else "tt", t.get("tile_blocks", 0),
+                                  t.get("wg_size", 0), t.get("grid_per_cu", 0),
+                                  t.get("blocks_per_lane", 0))
 
 
 @pytest.mark.parametrize("tune", TUNES, ids=_tune_id)
@@ -160,7 +164,10 @@ def test_batched_invalid_segments(oracle):
             assert np.array_equal(o[a:a + ln], exp), i
 
 
-@pytest.mark.parametrize("tune", [None, TUNES[4]], ids=["ttable", "bitslice"])
+BITSLICE_TUNE = next(t for t in TUNES if t and t["layout"] == am.LAYOUT_BITSLICE)
+
+
+@pytest.mark.parametrize("tune", [None, BITSLICE_TUNE], ids=["ttable", "bitslice"])
 def test_batched_invalid_key_schedule(oracle, tune):
     """A key slot whose schedule has no valid round count: its segments are
     left untouched and the status says AES_ERR_SEGMENT; the others are right."""
