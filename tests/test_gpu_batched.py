@@ -235,6 +235,44 @@ def test_batched_empty_runs_and_large_tables(oracle, nsegs, pattern):
     assert np.array_equal(o, exp)
 
 
+@pytest.mark.parametrize("tile,bpl", [(256, 4), (1024, 4), (1024, 2), (320, 4)])
+def test_batched_tile_remainders(oracle, tile, bpl):
+    """The last pass of a tile: every remainder of 1 to 256 blocks after the
+    whole four-block passes (one, two, three or four blocks per lane), with
+    and without a partial last block in each of its slots, counters aligned
+    and not aligned to 256-counter groups; outputs land in a buffer whose
+    other bytes must stay untouched."""
+    g = _rng(12 + tile + bpl)
+    rest = np.concatenate([np.arange(1, 257), g.integers(1, 257, size=60)])
+    whole = g.integers(0, 3, size=rest.size) * 256
+    tails = g.integers(0, 16, size=rest.size)
+    lengths = ((whole + rest - (tails > 0)) * 16 + tails).astype(np.int64)
+    n = lengths.size
+    in_off, total = wl.pack_offsets(lengths)
+    out_off = in_off + 16 * np.arange(n)              # a 16-byte gap after every message
+    keys = [g.bytes(16), g.bytes(32)]
+    slots = (np.arange(n) % 2).astype(np.uint32)
+    nonces = np.frombuffer(g.bytes(12 * n), np.uint8).reshape(n, 12)
+    ctr0 = np.where(np.arange(n) % 3 == 0, 0, g.integers(0, 2 ** 24, size=n)).astype(np.uint32)
+    segs_h = bt.segment_table(in_off, out_off, lengths, slots, ctr0, nonces)
+    pt = np.frombuffer(g.bytes(total + 16), np.uint8).copy()
+    x = torch.from_numpy(pt).to(DEV)
+    out = torch.full((total + 16 * n + 16,), 0xA5, dtype=torch.uint8, device=DEV)
+    ws = bt.workspace(n, DEV)
+    am.ctr_xcrypt_batched(torch.from_numpy(segs_h.view(np.uint8).copy()).to(DEV),
+                          key_table(keys), x, out, ws,
+                          {"layout": am.LAYOUT_TTABLE, "tile_blocks": tile, "blocks_per_lane": bpl})
+    assert am.batched_read_status(ws) == 0
+    o = out.cpu().numpy()
+    exp = np.full(o.size, 0xA5, np.uint8)
+    for i in range(n):
+        a, b, ln = int(in_off[i]), int(out_off[i]), int(lengths[i])
+        exp[b:b + ln] = oracle.ctr_xcrypt(keys[slots[i]], nonces[i].tobytes(), int(ctr0[i]),
+                                          pt[a:a + ln])
+    bad = np.flatnonzero(o != exp)
+    assert bad.size == 0, (bad[:8], lengths[np.searchsorted(out_off, bad[0], "right") - 1])
+
+
 def test_batched_graph_replays(mixed):
     """A captured graph replayed three times, the input rewritten in place with
     eager work and synchronizations in between; every replay equals an eager
