@@ -8,18 +8,20 @@
 // the caller's stream:
 //   1. prepare (one workgroup): validates every segment, counts its tiles,
 //      writes the exclusive prefix sums tile_start[0..nsegs] and clears the
-//      tile counter and the status word in the workspace.  Invalid segments
-//      get no tiles and set the status word to AES_ERR_SEGMENT (a key
-//      schedule without a valid round count is caught by the CTR kernel,
+//      16 claim counters and the status word in the workspace.  Invalid
+//      segments get no tiles and set the status word to AES_ERR_SEGMENT (a
+//      key schedule without a valid round count is caught by the CTR kernel,
 //      which skips the segment's tiles and sets the same status).
 //   2. persistent CTR kernel (a fixed grid of workgroups per CU): wave g of
 //      W (numbered workgroups fastest) takes tile g first, then claims
 //      tiles W + 16 k + p from one of 16 counters p (its own until that
-//      runs dry, then the next), finds the tile's segment with a 64-way ballot search over tile_start
-//      (three rounds for 10^4 segments), loads that segment's key schedule
-//      and nonce, and runs the T-table or the bitsliced round function on
-//      the tile.  The LDS tables are filled once per workgroup; they do not
-//      depend on the key.
+//      runs dry, then the next one its workgroup has not found empty),
+//      finds the tile's segment with a 64-way ballot search over tile_start
+//      (in LDS samples of it for the table kernel: two rounds for 10^4
+//      segments, then one round of global loads), loads that segment's key
+//      schedule and nonce, and runs the T-table or the bitsliced round
+//      function on the tile.  The LDS tables are filled once per workgroup;
+//      they do not depend on the key.
 // Neither kernel uses a memset, so the pair can be captured in a HIP graph and
 // replayed after the segment table or the data have been rewritten in place.
 #include <hip/hip_runtime.h>
