@@ -183,6 +183,15 @@ def batched_leg():
 
 
 SERVING_WARMUP = 5000
+# Batch limits of the C++ serving loop.  Measured with 1,024 key rows (five
+# runs each on two boxes): a 64 / 128 / 256 MiB byte limit gave closed-loop
+# capacities of 33.0-36.4 / 35.1-38.5 / 37.0-42.0 M requests/s with the same
+# latency at a fixed offered load (p50 / p99 at 18-20 M requests/s:
+# 0.054-0.059 / 0.090-0.125 ms for all three; at 32 M: 0.107-0.129 /
+# 0.201-0.230 ms): under load batches stay well below the limit, and a
+# backlog drains in fewer, larger launches.
+SERVING_BATCH_BYTES = 256 << 20
+SERVING_BATCH_REQS = 16384
 
 
 def serving_leg(nreq):
@@ -234,8 +243,9 @@ def serving_leg(nreq):
             st, _ = srv.run(reqs)
         else:
             st, _ = serve.run_native(pool, rs.keys, reqs, nslots, nstreams=2,
-                                     hbm_budget=4 << 30, max_batch_reqs=8192,
-                                     window_s=25e-6, out=ob)
+                                     hbm_budget=4 << 30, max_batch_reqs=SERVING_BATCH_REQS,
+                                     max_batch_bytes=SERVING_BATCH_BYTES, window_s=25e-6,
+                                     out=ob)
         torch.cuda.synchronize()
         s = st.summary(skip=nwarm)
         if nwarm:
@@ -246,7 +256,9 @@ def serving_leg(nreq):
     run(1e5, 5000, 1024, closed=True)            # warm-up
     res_all = {"workload": "%d requests, lognormal sizes median 4 KiB sigma 2 (<=16 MiB), "
                            "1024 keys (half AES-128, half AES-256), 4 GiB budget" % nreq,
-               "loop": "aes_serve_run (C++), 2 streams"}
+               "loop": "aes_serve_run (C++), 2 streams, batches up to %d MiB / %d requests, "
+                       "25 us window" % (SERVING_BATCH_BYTES >> 20, SERVING_BATCH_REQS),
+               "python_loop": "serve.Server, batches up to 64 MiB / 8192 requests"}
     for nslots in (1024, 256):
         cap = run(1e5, nreq, nslots, closed=True)
         rate = cap["req_per_s"]
