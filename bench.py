@@ -187,7 +187,7 @@ SERVING_WARMUP = 5000
 # runs each on two boxes): a 64 / 128 / 256 MiB byte limit gave closed-loop
 # capacities of 33.0-36.4 / 35.1-38.5 / 37.0-42.0 M requests/s with the same
 # latency at a fixed offered load (p50 / p99 at 18-20 M requests/s:
-# 0.054-0.059 / 0.090-0.125 ms for all three; at 32 M: 0.107-0.129 /
+# 0.054-0.060 / 0.090-0.125 ms for all three; at 32 M: 0.107-0.129 /
 # 0.201-0.230 ms): under load batches stay well below the limit, and a
 # backlog drains in fewer, larger launches.
 SERVING_BATCH_BYTES = 256 << 20
