@@ -111,20 +111,26 @@ def test_native_rejects_oversize():
     assert res[8] is not None and res[8].numel() == int(reqs.size[8])
 
 
-@pytest.mark.parametrize("max_batch_mib", [4, 12, 48])
-def test_native_batch_sizes_cover_every_tile(oracle, max_batch_mib):
-    """Backlogged requests of up to 2 MiB cut into batches of about
-    max_batch_mib MiB: the loop runs them with 256-, 512- and 1,024-block
-    tiles respectively; every output equals the request run alone, and a
-    sample equals the oracle."""
-    nreq, pool_bytes = 400, 64 << 20
-    rs = wl.serving_inputs(nreq, 1e5, nkeys=24, median=128 << 10, sigma=1.0,
-                           max_size=2 << 20, seed=40 + max_batch_mib)
+@pytest.mark.parametrize("max_batch_mib,nreq,median_kib", [(4, 400, 128), (48, 400, 128),
+                                                          (160, 700, 640)])
+def test_native_batch_sizes_cover_every_tile(oracle, max_batch_mib, nreq, median_kib):
+    """Backlogged requests cut into batches of about max_batch_mib MiB: the
+    loop runs batches of up to 2,048 blocks per wave of its grid (128 MiB on
+    256 CUs) with 256-block tiles and larger ones with 1,024-block tiles;
+    every output equals the request run alone, and a sample equals the
+    oracle."""
+    pool_bytes = 64 << 20
+    rs = wl.serving_inputs(nreq, 1e5, nkeys=24, median=median_kib << 10, sigma=1.0,
+                           max_size=(2 if median_kib < 512 else 8) << 20,
+                           seed=40 + max_batch_mib)
     reqs = serve.requests_from_stream(rs, pool_bytes, seed=41)
     g = np.random.Generator(np.random.PCG64(42))
     pool_h = np.frombuffer(g.bytes(pool_bytes), np.uint8).copy()
     pool = torch.from_numpy(pool_h).to(DEV)
-    st, res = serve.run_native(pool, rs.keys, reqs, nslots=8, nstreams=2, hbm_budget=1 << 30,
+    if max_batch_mib > 128:
+        waves = 16 * am.device_cu_count()
+        assert int(reqs.size.sum()) > 2 * (2048 * 16 * waves)   # batches above the threshold
+    st, res = serve.run_native(pool, rs.keys, reqs, nslots=8, nstreams=2, hbm_budget=2 << 30,
                                max_batch_bytes=max_batch_mib << 20, realtime=False)
     torch.cuda.synchronize()
     assert st.completed == nreq and st.rejected == 0
