@@ -304,6 +304,29 @@ def test_stream_4gib_sampled(oracle):
 
 
 @pytest.mark.slow
+def test_stream_4gib_every_tuner_candidate(oracle):
+    """The benchmark autotunes the 4 GiB launch and times the winner, which
+    differs from box to box: every candidate launch shape the tuner tries
+    (layout, workgroup size, grid, blocks per lane) must give, over the whole
+    4 GiB, exactly the default launch's output, which a sample of blocks ties
+    to the oracle here (and every byte does in test_stream_4gib_full_oracle)."""
+    from paper_1506_08503_amd import autotune
+    inp = wl.stream_4g_inputs()
+    x = fill_device(inp)
+    ks = am.key_schedule(inp.key)
+    ref = am.ctr_xcrypt(ks, inp.nonce, inp.ctr0, x)
+    n = check_stream_sample(oracle, inp, x, ref, _rng(321))
+    assert n > 100_000
+    y = torch.empty_like(x)
+    cands = autotune.plain_candidates("ctr")
+    assert len(cands) > 40
+    for cand in cands:
+        y.fill_(0)
+        am.ctr_xcrypt(ks, inp.nonce, inp.ctr0, x, out=y, **cand)
+        assert torch.equal(y, ref), cand
+
+
+@pytest.mark.slow
 def test_stream_sharded_equals_whole():
     """The multi-GPU split (block range g of G with ctr0 + start_g), run on one
     GPU: eight 512 MiB shards give the same 4 GiB output as one call."""
