@@ -318,8 +318,9 @@ def test_autotune_small():
 def test_batched_full_workload(oracle):
     """10,000 messages, log-uniform 1 B .. 1 MiB, own AES-128 keys and nonces
     (0.68 GiB): one persistent launch equals 10,000 plain launches byte for
-    byte, and the oracle agrees on every byte of every message (about 10 s on
-    16 host threads)."""
+    byte, so does every launch shape the benchmark's autotuner tries (it
+    times whichever wins on the box), and the oracle agrees on every byte of
+    every message (about 10 s on 16 host threads)."""
     b = wl.batched_inputs()
     db = bt.DeviceBatch(b, DEV)
     got = db.run().clone()
@@ -327,6 +328,11 @@ def test_batched_full_workload(oracle):
     db.out.zero_()
     loop = db.run_plain_loop().clone()
     assert torch.equal(got, loop)
+    for cand in autotune.candidates():
+        db.out.zero_()
+        db.run(cand)
+        assert db.status() == 0, cand
+        assert torch.equal(db.out, got), cand
     pt = db.x.cpu().numpy()
     out = got.cpu().numpy()
 
