@@ -57,6 +57,50 @@ def test_served_equals_alone(oracle):
     assert s["p99_ms"] >= s["p50_ms"] > 0
 
 
+@pytest.mark.parametrize("nslots", [1024, 256])
+def test_native_bench_configuration(oracle, nslots):
+    """The serving benchmark's configuration on a backlogged slice of its
+    workload: lognormal sizes (median 4 KiB, sigma 2, up to 16 MiB), 1,024
+    keys (half AES-128, half AES-256), a 256 MiB pool, a 4 GiB budget, two
+    streams, batches up to 256 MiB / 16,384 requests, a 25 us window, key
+    caches of 1,024 and 256 rows.  Every request equals the same request run
+    alone; a sample of 400 equals the oracle."""
+    nreq, pool_bytes = 20000, 256 << 20
+    rs = wl.serving_inputs(nreq, 1e5, nkeys=1024, seed=51)
+    reqs = serve.requests_from_stream(rs, pool_bytes, seed=52)
+    reqs.arrival[:] = 0.0
+    g = np.random.Generator(np.random.PCG64(53))
+    pool_h = np.frombuffer(g.bytes(pool_bytes), np.uint8).copy()
+    pool = torch.from_numpy(pool_h).to(DEV)
+    st, res = serve.run_native(pool, rs.keys, reqs, nslots, nstreams=2, hbm_budget=4 << 30,
+                               max_batch_reqs=16384, max_batch_bytes=256 << 20,
+                               window_s=25e-6)
+    torch.cuda.synchronize()
+    assert st.completed == nreq and st.rejected == 0
+    assert st.key_hits + st.key_misses == nreq
+    assert st.batches < nreq // 100 and st.max_inflight == 2     # backlogged: large batches
+    scheds = {}
+    for i in range(nreq):
+        kid = int(reqs.key_id[i])
+        if kid not in scheds:
+            scheds[kid] = am.key_schedule(rs.keys[kid], DEV)
+        a, n = int(reqs.in_off[i]), int(reqs.size[i])
+        alone = am.ctr_xcrypt(scheds[kid], reqs.nonce[i].tobytes(), int(reqs.ctr0[i]),
+                              pool[a:a + n])
+        assert torch.equal(res[i], alone), i
+    sample = np.random.Generator(np.random.PCG64(54)).choice(nreq, 400, replace=False)
+    got = {int(i): res[int(i)].cpu().numpy() for i in sample}
+
+    def agrees(i):
+        a, n = int(reqs.in_off[i]), int(reqs.size[i])
+        exp = oracle.ctr_xcrypt(rs.keys[reqs.key_id[i]], reqs.nonce[i].tobytes(),
+                                int(reqs.ctr0[i]), pool_h[a:a + n])
+        return np.array_equal(got[i], exp)
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as pool_ex:
+        bad = [i for i, ok in zip(got, pool_ex.map(agrees, list(got))) if not ok]
+    assert not bad, bad[:10]
+
+
 @pytest.mark.parametrize("nstreams,realtime", [(2, True), (4, False), (1, True), (3, True),
                                                (8, False)])
 def test_native_served_equals_alone(oracle, nstreams, realtime):
