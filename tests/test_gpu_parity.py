@@ -30,7 +30,8 @@ def _rng(seed):
 
 
 def _to_dev(a):
-    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    # a copy: inputs made from bytes objects are read-only arrays
+    return torch.from_numpy(np.array(a, copy=True, order="C")).to(DEV)
 
 
 def _host(t):
