@@ -251,10 +251,11 @@ __device__ __forceinline__ uint32_t find_segment_sampled(const uint32_t *smp,
 // 256-block tiles 2.20 ms (claim bound); static first tiles and 16 counters
 // 0.452 and 0.72 ms.  The mask: 64 MiB of lognormal request sizes (2,299
 // messages, 5,730 tiles of 1,024 blocks) 92.7 -> 68.8 us, 16,384 messages of
-// 4 KiB 125 -> 89 us, 10^4 messages 0.429 ms at 1,024 blocks.  A plain load of the counter before each add (to skip
-// adds on exhausted counters) made every tile size slower, and claiming
-// chunks of consecutive tiles per add was slower at 2048-4096 blocks per tile
-// (waves then stream through separate regions).
+// 4 KiB 125 -> 89 us, 10^4 messages 0.429 ms at 1,024 blocks.  A plain load
+// of the counter before each add (to skip adds on exhausted counters) made
+// every tile size slower, and claiming chunks of consecutive tiles per add
+// was slower at 2048-4096 blocks per tile (waves then stream through
+// separate regions).
 __device__ __forceinline__ uint32_t claim_tile(void *ws, uint32_t *dry, uint32_t &part,
                                                uint32_t dyn0, uint32_t ntiles, uint32_t lane)
 {
