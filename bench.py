@@ -14,6 +14,9 @@ Besides the throughput it reports
   * gcm: AES-128-GCM over the same buffer (encrypt, decrypt) and the GHASH
     passes alone, with their HBM and LDS fractions;
   * batched / serving: many-message launches and the request loop;
+  * sweep: the paper's Fig. 3 workloads (CBC and CTR against message count
+    and length);
+  * dbcolumn: AES-256 ECB over the 2^26-row database column;
   * cpu_baseline: the CPU oracle (plain algebraic AES) timed on the host's
     cores over a bounded sample of the same workload.
 """
