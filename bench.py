@@ -318,7 +318,7 @@ def sweep_fig3():
     return {"sweep": "paper Fig. 3 workloads, AES-128", "rows": rows}
 
 
-# Measured on the box (rocprofv3 --pmc SQ_INSTS_VALU, AES-128 CTR over 4 GiB):
+# Measured on an MI355X (rocprofv3 --pmc SQ_INSTS_VALU, AES-128 CTR over 4 GiB):
 # VALU lane operations per block of ctr_grouped_kernel.
 CTR_VALU_PER_BLOCK = 207
 
@@ -559,8 +559,9 @@ def load_traffic(path, kernel):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the AES path needs no cross-GPU exchange "
-              "and this build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: the AES path needs no cross-GPU exchange; "
+              "a multi-GPU run is one independent process per GPU over its own block "
+              "range (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.trace_summary:
         print(json.dumps(trace_summary(args.trace_summary, args.last, args.split_gap_ms)),
