@@ -48,7 +48,8 @@ class SimClock:
 
 class SimExecutor:
     """One batch at a time in submission order: a batch submitted at t ends at
-    max(t, previous end) + latency + payload bytes / rate (the driver's model)."""
+    max(t, previous end) + latency + payload bytes / rate (the model of the simulated
+    device in serve_loop_driver.cpp)."""
 
     def __init__(self, clock, nstreams, latency, rate, tick):
         self.clock, self.nstreams = clock, nstreams
